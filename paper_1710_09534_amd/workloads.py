@@ -1,0 +1,307 @@
+"""Seeded synthetic inputs for the ternary wetting lattice Boltzmann solver.
+
+This module builds the *inputs* of a solve -- grid, solid geometry, contact
+angles, fluid properties and initial order-parameter / velocity fields -- for
+the paper's workload shapes.  It contains none of the method's arithmetic and
+is the only module shared by the GPU path and the FP64 oracle.
+
+Initial profiles follow the smooth tanh drop of the paper's set-ups (Sec. III,
+Eqs. 46, 50, 56), read as c = 1/2 + 1/2 tanh(2 (R - r) / D) with r the
+Euclidean distance to the drop centre; a compound drop takes
+c_core = profile(R_core) and c_shell = profile(R_shell) - c_core (Eq. 56).
+Flat walls are the solid rows 0 and ny-1; a wall surface lies half a link
+from the first fluid row (Sec. II.B), so a drop "centred on the bottom wall"
+has y_c = 0.5.
+
+Random numbers come from SplitMix64 (Steele, Lea & Flood 2014), implemented
+here so that both solvers receive identical arrays.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+_MASK = (1 << 64) - 1
+
+
+def splitmix64(seed: int, n: int) -> np.ndarray:
+    """First n outputs of SplitMix64 started from ``seed`` (uint64 array)."""
+    out = np.empty(n, dtype=np.uint64)
+    s = seed & _MASK
+    for i in range(n):
+        s = (s + 0x9E3779B97F4A7C15) & _MASK
+        z = s
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK
+        out[i] = z ^ (z >> 31)
+    return out
+
+
+def uniform(seed: int, n: int, lo: float = 0.0, hi: float = 1.0) -> np.ndarray:
+    """n doubles in [lo, hi) from the top 53 bits of SplitMix64 outputs."""
+    u = (splitmix64(seed, n) >> np.uint64(11)).astype(np.float64) * (1.0 / (1 << 53))
+    return lo + (hi - lo) * u
+
+
+class Rng:
+    """Sequential scalar draws from one SplitMix64 stream."""
+
+    def __init__(self, seed: int):
+        self.s = seed & _MASK
+
+    def next_u64(self) -> int:
+        self.s = (self.s + 0x9E3779B97F4A7C15) & _MASK
+        z = self.s
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK
+        return z ^ (z >> 31)
+
+    def uniform(self, lo: float = 0.0, hi: float = 1.0) -> float:
+        return lo + (hi - lo) * ((self.next_u64() >> 11) * (1.0 / (1 << 53)))
+
+    def choice(self, n: int) -> int:
+        return int(self.uniform() * n) % n
+
+
+# ----------------------------------------------------------------- geometry
+def coords(nx: int, ny: int):
+    y, x = np.mgrid[0:ny, 0:nx]
+    return x.astype(np.float64), y.astype(np.float64)
+
+
+def tanh_drop(nx, ny, xc, yc, R, D):
+    """Smooth disc indicator 1/2 + 1/2 tanh(2 (R - r) / D)."""
+    x, y = coords(nx, ny)
+    r = np.sqrt((x - xc) ** 2 + (y - yc) ** 2)
+    return 0.5 + 0.5 * np.tanh(2.0 * (R - r) / D)
+
+
+def channel_mask(nx, ny, bottom=1, top=2):
+    """Solid rows 0 (material ``bottom``) and ny-1 (material ``top``)."""
+    m = np.zeros((ny, nx), dtype=np.uint8)
+    m[0, :] = bottom
+    m[ny - 1, :] = top
+    return m
+
+
+def cylinder_mask(nx, ny, xc, yc, R, material=1):
+    x, y = coords(nx, ny)
+    m = np.zeros((ny, nx), dtype=np.uint8)
+    m[(x - xc) ** 2 + (y - yc) ** 2 <= R * R] = material
+    return m
+
+
+def fluid(sigma=(1e-3, 1e-3, 1e-3), D=4.0, M0=1e-4, tau=(0.8, 0.8), rho=(1.0, 1.0, 1.0),
+          nu=(0.1, 0.1, 0.1), gravity=(0.0, 0.0)) -> dict:
+    return {"sigma12": float(sigma[0]), "sigma13": float(sigma[1]), "sigma23": float(sigma[2]),
+            "D": float(D), "M0": float(M0), "tau1": float(tau[0]), "tau2": float(tau[1]),
+            "rho": [float(r) for r in rho], "nu": [float(v) for v in nu],
+            "gravity": [float(g) for g in gravity]}
+
+
+def material(theta13, theta23, wall_u=(0.0, 0.0)) -> dict:
+    return {"theta13": float(theta13), "theta23": float(theta23),
+            "wall_u": [float(wall_u[0]), float(wall_u[1])]}
+
+
+def admissible(sigma12, sigma13, sigma23, theta13=None, theta23=None) -> bool:
+    """Acceptance rule of the sampled inputs: the surface tensions must give
+    lambda_i > 0 and lambda_i > lambda_T / 2 (the admissible range stated with
+    Eq. 7), and the prescribed angles must give |cos theta12| <= 1 (Eq. 39)."""
+    lam = (sigma12 + sigma13 - sigma23, sigma12 + sigma23 - sigma13,
+           sigma13 + sigma23 - sigma12)
+    if min(lam) <= 0:
+        return False
+    lam_t = 3.0 / sum(1.0 / v for v in lam)
+    if min(lam) <= 0.5 * lam_t:
+        return False
+    if theta13 is not None:
+        c = (sigma13 * math.cos(math.radians(theta13))
+             - sigma23 * math.cos(math.radians(theta23))) / sigma12
+        if abs(c) > 1.0:
+            return False
+    return True
+
+
+def sample_sigma(rng: Rng, lo=5e-4, hi=2e-3, theta13=None, theta23=None, max_draws=100000):
+    draws = 0
+    while True:
+        draws += 1
+        s = (rng.uniform(lo, hi), rng.uniform(lo, hi), rng.uniform(lo, hi))
+        if admissible(*s, theta13=theta13, theta23=theta23):
+            return s, draws
+        if draws > max_draws:
+            raise RuntimeError("no admissible surface tensions")
+
+
+def _problem(name, nx, ny, fl, periodic, mask, mats, c1, c2, ux=None, uy=None, steps=0,
+             **extra):
+    solid = mask != 0
+    c1 = np.where(solid, 0.0, c1)
+    c2 = np.where(solid, 0.0, c2)
+    p = {"name": name, "nx": nx, "ny": ny, "fluid": fl, "periodic": periodic,
+         "material": np.ascontiguousarray(mask, dtype=np.uint8), "mats": mats,
+         "c1": np.ascontiguousarray(c1), "c2": np.ascontiguousarray(c2),
+         "ux": None if ux is None else np.ascontiguousarray(np.where(solid, 0.0, ux)),
+         "uy": None if uy is None else np.ascontiguousarray(np.where(solid, 0.0, uy)),
+         "steps": steps}
+    p.update(extra)
+    return p
+
+
+# ------------------------------------------------------------------ configs
+def reduction_case(nx=64, ny=64, R=16.0, theta13=60.0, sigma=(1e-3, 1e-3, 1e-3), seed=1,
+                   noise=1e-6, steps=2000, theta23=90.0):
+    """Semicircular phase-1 drop on the bottom wall of a channel, phase 2
+    absent (64x64, R = 16, 60 deg, sigma = 1e-3, noise 1e-6 on c1)."""
+    D = 4.0
+    mask = channel_mask(nx, ny)
+    mats = [material(theta13, theta23), material(90.0, 90.0)]
+    c1 = tanh_drop(nx, ny, nx / 2.0, 0.5, R, D)
+    if noise:
+        c1 = c1 + uniform(seed, nx * ny, -noise, noise).reshape(ny, nx)
+    c2 = np.zeros((ny, nx))
+    fl = fluid(sigma=sigma, D=D, M0=0.1 * sigma[1], tau=(0.8, 0.8), rho=(1, 1, 1),
+               nu=(0.1, 0.1, 0.1))
+    return _problem("reduction_%dx%d" % (nx, ny), nx, ny, fl, (1, 0), mask, mats, c1, c2,
+                    steps=steps, R=R, theta=theta13)
+
+
+def binary_drops(seed=0, nx=256, ny=128, R=24.0, steps=20000):
+    """Adjacent phase-1 and phase-2 semicircles (R = 24) touching at x = nx/2
+    on the bottom wall; sigma_ij ~ U[5e-4, 2e-3] (admissible draws);
+    theta13 = 60, theta23 = 120; densities 10/5/1."""
+    D = 4.0
+    rng = Rng(seed)
+    th13, th23 = 60.0, 120.0
+    sig, draws = sample_sigma(rng, theta13=th13, theta23=th23)
+    mask = channel_mask(nx, ny)
+    mats = [material(th13, th23), material(90.0, 90.0)]
+    c1 = tanh_drop(nx, ny, nx / 2.0 - R, 0.5, R, D)
+    c2 = tanh_drop(nx, ny, nx / 2.0 + R, 0.5, R, D)
+    s = np.minimum(c1 + c2, 1.0)
+    over = (c1 + c2) > 1.0
+    c2 = np.where(over, s - c1, c2)
+    fl = fluid(sigma=sig, D=D, M0=0.1 * (sum(sig) / 3.0), tau=(0.8, 0.8), rho=(10, 5, 1),
+               nu=(0.1, 0.1, 0.1))
+    return _problem("binary_drops_%dx%d_s%d" % (nx, ny, seed), nx, ny, fl, (1, 0), mask, mats,
+                    c1, c2, steps=steps, sigma_draws=draws, R=R)
+
+
+def compound_shear(seed=0, nx=512, ny=256, U=0.01, R_core=20.0, R_shell=40.0, steps=50000):
+    """Phase-2 core inside a phase-1 shell resting on the bottom wall; walls
+    move at -U (bottom) and +U (top); theta13 ~ U[45, 135], theta23 = 90;
+    equal sigma from Ca = rho nu (2U/(ny-2)) R_shell / sigma, Ca ~ U[0.1, 0.3]."""
+    D = 4.0
+    rng = Rng(seed)
+    while True:
+        th13 = rng.uniform(45.0, 135.0)
+        ca = rng.uniform(0.1, 0.3)
+        rho, nu = 1.0, 0.1
+        gdot = 2.0 * U / (ny - 2)
+        sig = rho * nu * gdot * R_shell / ca
+        if admissible(sig, sig, sig, theta13=th13, theta23=90.0):
+            break
+    mask = channel_mask(nx, ny)
+    mats = [material(th13, 90.0, wall_u=(-U, 0.0)), material(90.0, 90.0, wall_u=(U, 0.0))]
+    yc = 0.5 + R_shell
+    core = tanh_drop(nx, ny, nx / 2.0, yc, R_core, D)
+    shell = tanh_drop(nx, ny, nx / 2.0, yc, R_shell, D) - core
+    fl = fluid(sigma=(sig, sig, sig), D=D, M0=0.1 * sig, tau=(0.8, 0.8), rho=(1, 1, 1),
+               nu=(nu, nu, nu))
+    return _problem("compound_shear_%dx%d_s%d" % (nx, ny, seed), nx, ny, fl, (1, 0), mask,
+                    mats, shell, core, steps=steps, theta13=th13, Ca=ca, U=U)
+
+
+def cylinder_impact(We=10.0, theta=90.0, nx=1024, ny=2048, R_cyl=128.0, R_shell=96.0,
+                    R_core=48.0, sigma=5e-3, steps=100000):
+    """Compound drop (phase-1 core, phase-2 shell) falling onto a staircase
+    cylinder in a fully periodic box; theta13 = theta23 = theta, theta12 = 90;
+    densities 10/10/1; U = sqrt(We sigma_bar / (rho_bar xi)), xi = 2 R_shell
+    (the Weber number of Eq. 55)."""
+    D = 4.0
+    xi = 2.0 * R_shell
+    rho_bar = 10.0
+    U = math.sqrt(We * sigma / (rho_bar * xi))
+    xc, yc = nx / 2.0, ny / 2.0
+    mask = cylinder_mask(nx, ny, xc, yc, R_cyl)
+    mats = [material(theta, theta)]
+    ydrop = yc + R_cyl + R_shell
+    core = tanh_drop(nx, ny, xc, ydrop, R_core, D)
+    shell = tanh_drop(nx, ny, xc, ydrop, R_shell, D) - core
+    uy = -U * (core + shell)
+    ux = np.zeros_like(uy)
+    fl = fluid(sigma=(sigma, sigma, sigma), D=D, M0=0.1 * sigma, tau=(0.8, 0.8),
+               rho=(10, 10, 1), nu=(0.1, 0.1, 0.1))
+    return _problem("cylinder_impact_%dx%d_We%g_th%g" % (nx, ny, We, theta), nx, ny, fl,
+                    (1, 1), mask, mats, core, shell, ux, uy, steps=steps, U=U, We=We)
+
+
+def free_drop(nx=64, ny=64, R=16.0, sigma=1e-3, D=4.0, steps=2000, rho=(1, 1, 1),
+              phase=1):
+    """Drop of phase ``phase`` in phase 3 in a fully periodic box (no solid)."""
+    mask = np.zeros((ny, nx), dtype=np.uint8)
+    c = tanh_drop(nx, ny, nx / 2.0, ny / 2.0, R, D)
+    z = np.zeros((ny, nx))
+    c1, c2 = (c, z) if phase == 1 else (z, c)
+    fl = fluid(sigma=(sigma, sigma, sigma), D=D, M0=0.1 * sigma, rho=rho)
+    return _problem("free_drop_%dx%d_R%g" % (nx, ny, R), nx, ny, fl, (1, 1), mask, [], c1, c2,
+                    steps=steps, R=R)
+
+
+def random_fields(nx, ny, seed=7, amp=0.2, geometry="channel", U=0.0, rho=(1.0, 1.0, 1.0),
+                  sigma=(1e-3, 1.3e-3, 1.1e-3), thetas=((60.0, 100.0), (120.0, 75.0)),
+                  gravity=(0.0, 0.0)):
+    """Smooth random three-phase mixture (sums of low-order Fourier modes) for
+    parity tests: exercises every term with all three phases present."""
+    x, y = coords(nx, ny)
+    rng = Rng(seed)
+
+    def smooth():
+        f = np.zeros((ny, nx))
+        for _ in range(4):
+            kx, ky = rng.choice(3) + 1, rng.choice(3) + 1
+            ph1, ph2 = rng.uniform(0, 2 * math.pi), rng.uniform(0, 2 * math.pi)
+            f += np.sin(2 * math.pi * kx * x / nx + ph1) * np.cos(2 * math.pi * ky * y / ny + ph2)
+        return f / 4.0
+
+    a, b = smooth(), smooth()
+    c1 = 1.0 / 3.0 + amp * a
+    c2 = 1.0 / 3.0 + amp * b
+    ux = 0.01 * smooth()
+    uy = 0.01 * smooth()
+    if geometry == "channel":
+        mask = channel_mask(nx, ny)
+        periodic = (1, 0)
+        mats = [material(*thetas[0], wall_u=(-U, 0.0)), material(*thetas[1], wall_u=(U, 0.0))]
+    elif geometry == "cylinder":
+        mask = cylinder_mask(nx, ny, nx / 2.0, ny / 2.0, min(nx, ny) / 5.0)
+        periodic = (1, 1)
+        mats = [material(*thetas[0])]
+    elif geometry == "box":
+        mask = np.zeros((ny, nx), dtype=np.uint8)
+        mask[0, :] = 1
+        mask[-1, :] = 2
+        mask[:, 0] = 1
+        mask[:, -1] = 2
+        periodic = (0, 0)
+        mats = [material(*thetas[0]), material(*thetas[1])]
+    else:
+        mask = np.zeros((ny, nx), dtype=np.uint8)
+        periodic = (1, 1)
+        mats = []
+    fl = fluid(sigma=sigma, D=4.0, M0=1e-4, tau=(0.8, 0.9), rho=rho, nu=(0.1, 0.05, 0.15),
+               gravity=gravity)
+    return _problem("random_%s_%dx%d_s%d" % (geometry, nx, ny, seed), nx, ny, fl, periodic, mask,
+                    mats, c1, c2, ux, uy, steps=0)
+
+
+def bandwidth_case(nx, ny):
+    """Cylinder geometry without a drop (pure phase 3 at rest): the memory
+    sweep workload."""
+    mask = cylinder_mask(nx, ny, nx / 2.0, ny / 2.0, min(nx, ny) / 8.0)
+    z = np.zeros((ny, nx))
+    fl = fluid(sigma=(5e-3,) * 3, M0=5e-4, rho=(10, 10, 1))
+    return _problem("sweep_%dx%d" % (nx, ny), nx, ny, fl, (1, 1), mask, [material(90, 90)],
+                    z, z, steps=500)
