@@ -1,0 +1,172 @@
+/*
+ * tlb.h -- C ABI of the MI355X ternary wetting lattice Boltzmann library.
+ *
+ * The library advances the ternary phase-field lattice Boltzmann model of
+ * Liang, Xu, Chen, Chai & Shi, "Lattice Boltzmann modeling of wall-bounded
+ * ternary fluid flows" (arXiv:1710.09534) on one AMD Instinct MI355X (gfx950):
+ * two order-parameter LB equations and one hydrodynamic LB equation on a D2Q9
+ * lattice (Sec. II.A, Eqs. 1-20), with the paper's ternary wetting boundary
+ * scheme at solid-adjacent fluid nodes and half-way bounce-back at solid
+ * links (Sec. II.B, Eqs. 40-45).
+ *
+ * Conventions (all calls):
+ *  - Lattice units, dx = dt = 1 (Sec. II.A).
+ *  - Host fields are row-major doubles, x fastest: value(x, y) = a[y*nx + x],
+ *    y = 0 is the bottom row.
+ *  - material[y*nx + x] == 0 marks a fluid node; m >= 1 a solid node of
+ *    material mats[m-1].  A solid wall surface lies half a link from the
+ *    adjacent fluid node (Sec. II.B).  In a non-periodic direction every node
+ *    on the domain edge must be solid.
+ *  - Every call returns a tlb_status (0 = TLB_OK); nothing throws across the
+ *    ABI.  Errors are checked in the order EINVAL (null pointer, bad size),
+ *    EPARAM (inadmissible physics), ESTATE (call order), EDIVERGED, EDEVICE.
+ *    A failed call leaves the context unchanged, except EDIVERGED, after
+ *    which only read_fields, read_populations, checkpoint_save, mass and
+ *    destroy are allowed.  tlb_last_error() gives the message.
+ *  - Host arrays are borrowed for the duration of the call only.
+ *  - A context is not thread-safe.  Contexts on different streams may run
+ *    concurrently.
+ */
+#ifndef TLB_H
+#define TLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TLB_OK = 0,
+    TLB_EINVAL = -1,    /* null pointer, size or buffer mismatch */
+    TLB_EPARAM = -2,    /* physics parameters outside the admissible range */
+    TLB_ENOMEM = -3,    /* workspace too small / allocation failed */
+    TLB_EDEVICE = -4,   /* HIP error; tlb_last_error() carries its text */
+    TLB_EDIVERGED = -5, /* a NaN/Inf order parameter was detected */
+    TLB_ESTATE = -6,    /* call out of order (e.g. step before init) */
+    TLB_EBUSY = -7      /* server: no slot / budget, or request not finished */
+} tlb_status;
+
+/* Storage precision of the populations (arithmetic in brackets):
+ *  TLB_FP64    all 27 populations and the 4 history scalars in FP64 [FP64]
+ *  TLB_FP32    everything in FP32 [FP32]
+ *  TLB_FP16DEV the 25 moving populations f^i_{k!=0}, g_k as FP16 values
+ *              scaled by a per-family power of two; the rest populations
+ *              f^1_0, f^2_0 (carrying c_i) and the history in FP32 [FP32].
+ *              Mass sums are FP64 in every mode. */
+typedef enum { TLB_FP64 = 0, TLB_FP32 = 1, TLB_FP16DEV = 2 } tlb_precision;
+
+/* Fluid properties (Sec. II.A). */
+typedef struct {
+    double sigma12, sigma13, sigma23; /* pairwise surface tensions, Eq. 7 */
+    double D;                         /* interface thickness, Eq. 8 */
+    double M0;                        /* mobility scale: M_i = M0/lambda_i, Eq. 12 */
+    double tau1, tau2;                /* order-parameter relaxation times, Eq. 1a;
+                                         eta_i follows from M_i = eta_i c_s^2 (tau_i - 1/2),
+                                         Eq. 18a, one eta per component */
+    double rho[3], nu[3];             /* phase densities / kinematic viscosities, Eqs. 14-15;
+                                         local tau_g = nu/c_s^2 + 1/2, Eq. 18b */
+    double gravity[2];                /* body force G = rho * gravity (Sec. III.A) */
+} tlb_fluid;
+
+/* A solid material: its wettability and its tangential wall velocity. */
+typedef struct {
+    double theta13_deg, theta23_deg; /* static contact angles, Eq. 38; theta12 from Eq. 39 */
+    double wall_u[2];                /* wall velocity (bounce-back with the moving-wall
+                                        momentum term; 0 = the paper's resting wall) */
+} tlb_material;
+
+/* field bits of tlb_read_fields; fields are written in this bit order */
+enum {
+    TLB_F_C1 = 1u << 0, TLB_F_C2 = 1u << 1, TLB_F_C3 = 1u << 2, TLB_F_RHO = 1u << 3,
+    TLB_F_UX = 1u << 4, TLB_F_UY = 1u << 5, TLB_F_P = 1u << 6, TLB_F_MU1 = 1u << 7,
+    TLB_F_MU2 = 1u << 8, TLB_F_MU3 = 1u << 9, TLB_F_ALL = (1u << 10) - 1
+};
+
+typedef struct tlb_ctx tlb_ctx;
+
+/* Device workspace needed for an nx x ny lattice at precision p (bytes).
+ * Returns 0 for nx or ny < 3. */
+size_t tlb_workspace_bytes(int nx, int ny, tlb_precision p);
+
+/* Create a context on a caller-owned device workspace (at least
+ * tlb_workspace_bytes, 256-byte aligned, alive until tlb_destroy) and a HIP
+ * stream (hipStream_t, NULL = default stream).  Validates the fluid
+ * parameters (Eqs. 7, 9, 18): lambda_i > 0 and lambda_i > lambda_T/2,
+ * tau_i > 1/2, D > 0, M0 > 0, rho_i > 0, nu_i > 0 (else TLB_EPARAM).
+ * The library owns *out until tlb_destroy. */
+tlb_status tlb_create(int nx, int ny, tlb_precision p, const tlb_fluid* fl,
+                      void* dev_workspace, size_t ws_bytes, void* hip_stream,
+                      tlb_ctx** out);
+
+/* Solid geometry and wettability.  material: host uint8 [ny*nx]; mats[m-1]
+ * for each material id m in 1..n_mats (n_mats <= 15).  theta12 of each
+ * material is derived from Eq. 39 (sigma12 cos12 = sigma13 cos13 - sigma23
+ * cos23) and written to theta12_out[n_mats] in degrees when non-NULL;
+ * |cos theta12| > 1 is TLB_EPARAM.  Must precede tlb_init_fields. */
+tlb_status tlb_set_geometry(tlb_ctx* ctx, int periodic_x, int periodic_y,
+                            const uint8_t* material, const tlb_material* mats,
+                            int n_mats, double* theta12_out);
+
+/* Initial order parameters and velocity (host [ny*nx] each; ux/uy NULL =
+ * at rest).  The populations start at their equilibria (Eqs. 2a, 2b) with
+ * the chemical potential of the initial field (Eq. 8 with the wetting ghosts
+ * of Eq. 42), pressure 0, and the time-derivative history set to
+ * (c1, c2, ux, uy).  Values at solid nodes are ignored.  Synchronous. */
+tlb_status tlb_init_fields(tlb_ctx* ctx, const double* c1, const double* c2,
+                           const double* ux, const double* uy);
+
+/* Advance nsteps time steps, asynchronously on the context's stream.  Each
+ * step is one fused pass: streaming with bounce-back (Eq. 44), moments
+ * (Eqs. 13-15), wetting ghosts and chemical potentials (Eqs. 8, 20, 42),
+ * forces (Eqs. 11-12), pressure (Eq. 13c), collision (Eq. 45).  Every
+ * check_interval steps (tlb_set_check_interval, default 100) a mass/NaN
+ * reduction runs on the device; a NaN seen by an earlier check makes this
+ * call return TLB_EDIVERGED without stepping. */
+tlb_status tlb_step(tlb_ctx* ctx, int64_t nsteps);
+tlb_status tlb_set_check_interval(tlb_ctx* ctx, int64_t interval); /* 0 = never */
+int64_t    tlb_step_count(const tlb_ctx* ctx);
+
+/* Macroscopic fields at the current time, evaluated from the current
+ * populations exactly as a step would (Eqs. 3, 8, 13-15).  host_out holds
+ * popcount(field_mask) * ny*nx doubles, fields in bit order.  Solid nodes
+ * read 0.  Synchronizes the stream. */
+tlb_status tlb_read_fields(tlb_ctx* ctx, uint32_t field_mask, double* host_out);
+
+/* The 27 populations f(x,t) entering the next collision (after streaming
+ * and bounce-back): host [27][ny*nx] doubles, planes f1_0..8, f2_0..8,
+ * g_0..8.  Solid nodes read 0.  Synchronizes. */
+tlb_status tlb_read_populations(tlb_ctx* ctx, double* host_out);
+
+/* Sum of c1, c2, c3 over fluid nodes in FP64 (deterministic two-pass
+ * device reduction).  Returns TLB_EDIVERGED if any c is NaN/Inf.
+ * Synchronizes. */
+tlb_status tlb_mass(tlb_ctx* ctx, double out[3]);
+
+/* Checkpoint: populations, history, step count.  host_buf holds
+ * tlb_checkpoint_bytes bytes.  A restored context continues bitwise
+ * identically. */
+tlb_status tlb_checkpoint_bytes(const tlb_ctx* ctx, size_t* bytes);
+tlb_status tlb_checkpoint_save(tlb_ctx* ctx, void* host_buf);
+tlb_status tlb_checkpoint_load(tlb_ctx* ctx, const void* host_buf);
+
+/* Average device time of one step kernel over nsteps back-to-back launches
+ * (HIP events on the context's stream; advances the state by nsteps). */
+tlb_status tlb_time_steps(tlb_ctx* ctx, int64_t nsteps, double* ms_per_step);
+
+/* Kernel tile rows per workgroup (tuning knob; results are identical for
+ * every legal value).  rows in {2, 4, 8, 16}. */
+tlb_status tlb_set_tile_rows(tlb_ctx* ctx, int rows);
+
+/* Last error message of ctx, or of the calling thread's last failed
+ * tlb_create / server call when ctx is NULL. */
+const char* tlb_last_error(const tlb_ctx* ctx);
+
+/* Releases the context (not the caller's workspace).  NULL is a no-op. */
+void tlb_destroy(tlb_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TLB_H */

@@ -1,0 +1,54 @@
+"""Builds the HIP library ``libtlb.so`` in-tree for gfx950 with hipcc.
+
+    python -m paper_1710_09534_amd.build            # build
+    python -m paper_1710_09534_amd.build --resources  # also print VGPR/LDS use
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libtlb.so")
+SOURCES = ["tlb_kernels.hip", "tlb_host.cpp", "tlb_server.cpp"]
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+# Packed-FP32 instructions are disabled on purpose.
+HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-Wno-unused-command-line-argument", "-munsafe-fp-atomics"]
+
+
+def sources():
+    return [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+
+
+def build(resources: bool = False, verbose: bool = False) -> str:
+    objs = []
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    for src in sources():
+        obj = os.path.join(CSRC, os.path.basename(src) + ".o")
+        cmd = [HIPCC] + HIP_FLAGS + inc + ["-c", src, "-o", obj]
+        if src.endswith(".hip"):
+            cmd = [HIPCC, "-x", "hip"] + HIP_FLAGS + inc + ["-c", src, "-o", obj]
+            if resources:
+                cmd.insert(1, "-Rpass-analysis=kernel-resource-usage")
+        if verbose:
+            print(" ".join(cmd))
+        subprocess.run(cmd, check=True)
+        objs.append(obj)
+    tmp = LIB + ".tmp%d" % os.getpid()
+    subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs,
+                   check=True)
+    os.replace(tmp, LIB)
+    for o in objs:
+        os.remove(o)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(resources="--resources" in sys.argv, verbose="-v" in sys.argv)
+    print(LIB)

@@ -1,0 +1,534 @@
+// tlb_host.cpp -- host runtime of the C ABI declared in include/tlb.h:
+// parameter derivation and validation, workspace layout, launches,
+// health checks and checkpoints.  All device work goes to the context's
+// stream; the only host<->device traffic is at init, readout, mass and
+// checkpoint calls.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/tlb.h"
+#include "tlb_internal.h"
+
+using namespace tlb;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Layout {
+    int pitch;
+    size_t npad;
+    size_t pop_bytes;   // one lattice (27 planes)
+    size_t rest_off;    // P16: offset of the two FP32 rest planes inside a lattice
+    size_t hist_bytes;
+    size_t off_pop[2], off_hist, off_mat, off_mtab, off_stage, off_part, off_result;
+    size_t total;
+};
+
+size_t elem_bytes(int prec) { return prec == P64 ? 8 : (prec == P32 ? 4 : 2); }
+
+Layout make_layout(int nx, int ny, int prec) {
+    Layout L{};
+    L.pitch = int(align_up(size_t(nx), kTileX));
+    L.npad = size_t(ny) * L.pitch;
+    size_t planes = align_up(27 * L.npad * elem_bytes(prec), kAlign);
+    L.rest_off = planes;
+    if (prec == P16) planes += align_up(2 * L.npad * 4, kAlign);
+    L.pop_bytes = planes;
+    L.hist_bytes = align_up(4 * L.npad * (prec == P64 ? 8 : 4), kAlign);
+    size_t o = 0;
+    L.off_pop[0] = o; o += L.pop_bytes;
+    L.off_pop[1] = o; o += L.pop_bytes;
+    L.off_hist = o; o += L.hist_bytes;
+    L.off_mat = o; o += align_up(L.npad, kAlign);
+    L.off_mtab = o; o += align_up(kMatStride * (kMaxMaterials + 1) * sizeof(double), kAlign);
+    L.off_stage = o; o += align_up(size_t(27) * nx * ny * sizeof(double), kAlign);
+    L.off_part = o; o += align_up(kReduceBlocks * 4 * sizeof(double), kAlign);
+    L.off_result = o; o += kAlign;
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+struct tlb_ctx {
+    int nx, ny, prec;
+    tlb_fluid fl;
+    Layout L;
+    Grid grid;
+    char* ws;
+    hipStream_t stream;
+    Consts<double> c64;
+    Consts<float> c32;
+    double lambda[3], lambdaT, M[2], eta[2];
+    int px, py;
+    bool geometry = false, inited = false, diverged = false;
+    int64_t steps = 0;
+    int64_t check_interval = 100;
+    int64_t since_check = 0;
+    int cur = 0;  // lattice holding the current state
+    int n_mats = 0;
+    double mtab_host[kMatStride * (kMaxMaterials + 1)] = {};
+    double* health = nullptr;  // pinned host copy of the last mass result
+    bool health_pending = false;
+    std::string err;
+};
+
+namespace {
+
+tlb_status fail(tlb_ctx* c, tlb_status s, const std::string& m) {
+    if (c) c->err = m;
+    g_last_error = m;
+    return s;
+}
+
+tlb_status dev_fail(tlb_ctx* c, hipError_t e, const char* where) {
+    return fail(c, TLB_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+PopBuf popbuf(tlb_ctx* c, int which) {
+    char* base = c->ws + c->L.off_pop[which];
+    PopBuf b;
+    b.planes = base;
+    b.rest = c->prec == P16 ? reinterpret_cast<float*>(base + c->L.rest_off) : nullptr;
+    return b;
+}
+
+const void* consts_ptr(tlb_ctx* c) {
+    return c->prec == P64 ? static_cast<const void*>(&c->c64) : static_cast<const void*>(&c->c32);
+}
+
+template <typename R>
+void fill_consts(Consts<R>& k, const tlb_ctx* c) {
+    const tlb_fluid& f = c->fl;
+    k.drho1 = R(f.rho[0] - f.rho[2]);
+    k.drho2 = R(f.rho[1] - f.rho[2]);
+    k.rho3 = R(f.rho[2]);
+    k.dnu1 = R(f.nu[0] - f.nu[2]);
+    k.dnu2 = R(f.nu[1] - f.nu[2]);
+    k.nu3 = R(f.nu[2]);
+    k.itau1 = R(1.0 / f.tau1);
+    k.itau2 = R(1.0 / f.tau2);
+    k.fs1 = R(1.0 - 0.5 / f.tau1);
+    k.fs2 = R(1.0 - 0.5 / f.tau2);
+    k.eta1 = R(c->eta[0]);
+    k.eta2 = R(c->eta[1]);
+    k.am1 = R((f.rho[0] - f.rho[2]) * c->M[0]);
+    k.am2 = R((f.rho[1] - f.rho[2]) * c->M[1]);
+    k.lam1 = R(c->lambda[0]);
+    k.lam2 = R(c->lambda[1]);
+    k.lam3 = R(c->lambda[2]);
+    k.lamT = R(c->lambdaT);
+    k.k12D = R(12.0 / f.D);
+    k.k34D = R(0.75 * f.D);
+    k.k4D = R(4.0 / f.D);
+    k.gx = R(f.gravity[0]);
+    k.gy = R(f.gravity[1]);
+    for (int i = 0; i < 3; ++i) {
+        k.scale[i] = 1.0f;
+        k.iscale[i] = 1.0f;
+    }
+}
+
+void set_grid(tlb_ctx* c, int rows) {
+    c->grid.nx = c->nx;
+    c->grid.ny = c->ny;
+    c->grid.pitch = c->L.pitch;
+    c->grid.npad = long(c->L.npad);
+    c->grid.tile_rows = rows;
+    c->grid.tiles_x = (c->nx + kTileX - 1) / kTileX;
+    c->grid.tiles_y = (c->ny + rows - 1) / rows;
+}
+
+tlb_status run_mass(tlb_ctx* c) {
+    hipError_t e = launch_mass(c->prec, c->grid, consts_ptr(c),
+                               reinterpret_cast<uint8_t*>(c->ws + c->L.off_mat), popbuf(c, c->cur),
+                               reinterpret_cast<double*>(c->ws + c->L.off_part),
+                               reinterpret_cast<double*>(c->ws + c->L.off_result), c->stream);
+    if (e != hipSuccess) return dev_fail(c, e, "mass reduction");
+    return TLB_OK;
+}
+
+// reads the pinned copy of the last health check if it has landed
+void poll_health(tlb_ctx* c) {
+    if (!c->health_pending) return;
+    if (hipStreamQuery(c->stream) != hipSuccess) return;  // not finished: look next time
+    c->health_pending = false;
+    if (c->health[3] != 0.0) c->diverged = true;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t tlb_workspace_bytes(int nx, int ny, tlb_precision p) {
+    if (nx < 3 || ny < 3 || (p != TLB_FP64 && p != TLB_FP32 && p != TLB_FP16DEV)) return 0;
+    return make_layout(nx, ny, int(p)).total;
+}
+
+tlb_status tlb_create(int nx, int ny, tlb_precision p, const tlb_fluid* fl, void* dev_workspace,
+                      size_t ws_bytes, void* hip_stream, tlb_ctx** out) {
+    if (!out) return fail(nullptr, TLB_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!fl || !dev_workspace) return fail(nullptr, TLB_EINVAL, "null fluid or workspace");
+    if (nx < 3 || ny < 3) return fail(nullptr, TLB_EINVAL, "nx and ny must be >= 3");
+    if (p != TLB_FP64 && p != TLB_FP32 && p != TLB_FP16DEV)
+        return fail(nullptr, TLB_EINVAL, "unknown precision");
+    if (reinterpret_cast<uintptr_t>(dev_workspace) % kAlign)
+        return fail(nullptr, TLB_EINVAL, "workspace not 256-byte aligned");
+    Layout L = make_layout(nx, ny, int(p));
+    if (ws_bytes < L.total) return fail(nullptr, TLB_ENOMEM, "workspace too small");
+    // Eq. 7, Eq. 9
+    double lam[3] = {fl->sigma12 + fl->sigma13 - fl->sigma23,
+                     fl->sigma12 + fl->sigma23 - fl->sigma13,
+                     fl->sigma13 + fl->sigma23 - fl->sigma12};
+    for (double l : lam)
+        if (!(l > 0.0)) return fail(nullptr, TLB_EPARAM, "surface tensions give lambda_i <= 0");
+    double lamT = 3.0 / (1.0 / lam[0] + 1.0 / lam[1] + 1.0 / lam[2]);
+    for (double l : lam)
+        if (!(l > 0.5 * lamT))
+            return fail(nullptr, TLB_EPARAM, "surface tensions give lambda_i <= lambda_T/2");
+    if (!(fl->D > 0.0) || !(fl->M0 > 0.0)) return fail(nullptr, TLB_EPARAM, "D and M0 must be > 0");
+    if (!(fl->tau1 > 0.5) || !(fl->tau2 > 0.5)) return fail(nullptr, TLB_EPARAM, "tau_i must be > 1/2");
+    for (int i = 0; i < 3; ++i)
+        if (!(fl->rho[i] > 0.0) || !(fl->nu[i] > 0.0))
+            return fail(nullptr, TLB_EPARAM, "densities and viscosities must be > 0");
+    if (!std::isfinite(fl->gravity[0]) || !std::isfinite(fl->gravity[1]))
+        return fail(nullptr, TLB_EPARAM, "gravity must be finite");
+
+    tlb_ctx* c = new tlb_ctx();
+    c->nx = nx;
+    c->ny = ny;
+    c->prec = int(p);
+    c->fl = *fl;
+    c->L = L;
+    c->ws = static_cast<char*>(dev_workspace);
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    for (int i = 0; i < 3; ++i) c->lambda[i] = lam[i];
+    c->lambdaT = lamT;
+    const double cs2 = 1.0 / 3.0;
+    c->M[0] = fl->M0 / lam[0];                           // Eq. 12
+    c->M[1] = fl->M0 / lam[1];
+    c->eta[0] = c->M[0] / (cs2 * (fl->tau1 - 0.5));     // Eq. 18a per component
+    c->eta[1] = c->M[1] / (cs2 * (fl->tau2 - 0.5));
+    fill_consts(c->c64, c);
+    fill_consts(c->c32, c);
+    set_grid(c, 8);
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->health), 4 * sizeof(double)) != hipSuccess) {
+        delete c;
+        return fail(nullptr, TLB_ENOMEM, "pinned health word");
+    }
+    std::memset(c->health, 0, 4 * sizeof(double));
+    *out = c;
+    return TLB_OK;
+}
+
+tlb_status tlb_set_geometry(tlb_ctx* c, int periodic_x, int periodic_y, const uint8_t* material,
+                            const tlb_material* mats, int n_mats, double* theta12_out) {
+    if (!c || !material || n_mats < 0 || (n_mats > 0 && !mats))
+        return fail(c, TLB_EINVAL, "null pointer or negative material count");
+    if (n_mats > kMaxMaterials) return fail(c, TLB_EINVAL, "at most 15 materials");
+    const int nx = c->nx, ny = c->ny;
+    for (long i = 0; i < long(nx) * ny; ++i)
+        if (material[i] > n_mats) return fail(c, TLB_EINVAL, "material id exceeds n_mats");
+    if (!periodic_x)
+        for (int y = 0; y < ny; ++y)
+            if (!material[long(y) * nx] || !material[long(y) * nx + nx - 1])
+                return fail(c, TLB_EINVAL, "non-periodic x needs solid columns 0 and nx-1");
+    if (!periodic_y)
+        for (int x = 0; x < nx; ++x)
+            if (!material[x] || !material[long(ny - 1) * nx + x])
+                return fail(c, TLB_EINVAL, "non-periodic y needs solid rows 0 and ny-1");
+    double tab[kMatStride * (kMaxMaterials + 1)] = {};
+    std::vector<double> th12(size_t(n_mats > 0 ? n_mats : 1));
+    const double d2r = std::acos(-1.0) / 180.0;
+    for (int m = 0; m < n_mats; ++m) {
+        double c13 = std::cos(mats[m].theta13_deg * d2r);
+        double c23 = std::cos(mats[m].theta23_deg * d2r);
+        double c12 = (c->fl.sigma13 * c13 - c->fl.sigma23 * c23) / c->fl.sigma12;  // Eq. 39
+        if (!(std::fabs(c12) <= 1.0))
+            return fail(c, TLB_EPARAM, "contact angles give |cos theta12| > 1 (Eq. 39)");
+        if (!std::isfinite(mats[m].wall_u[0]) || !std::isfinite(mats[m].wall_u[1]))
+            return fail(c, TLB_EPARAM, "wall velocity must be finite");
+        double* t = &tab[kMatStride * (m + 1)];
+        t[0] = c12;
+        t[1] = c13;
+        t[2] = c23;
+        t[3] = mats[m].wall_u[0];
+        t[4] = mats[m].wall_u[1];
+        th12[size_t(m)] = std::acos(c12) / d2r;
+    }
+    // upload the padded material plane
+    std::vector<uint8_t> pad(c->L.npad, 0);
+    for (int y = 0; y < ny; ++y) std::memcpy(&pad[size_t(y) * c->L.pitch], material + long(y) * nx, size_t(nx));
+    hipError_t e = hipMemcpyAsync(c->ws + c->L.off_mat, pad.data(), pad.size(), hipMemcpyHostToDevice,
+                                  c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->ws + c->L.off_mtab, tab, sizeof(tab), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return dev_fail(c, e, "set_geometry upload");
+    std::memcpy(c->mtab_host, tab, sizeof(tab));
+    c->n_mats = n_mats;
+    c->px = periodic_x != 0;
+    c->py = periodic_y != 0;
+    c->geometry = true;
+    c->inited = false;
+    if (theta12_out)
+        for (int m = 0; m < n_mats; ++m) theta12_out[m] = th12[size_t(m)];
+    return TLB_OK;
+}
+
+tlb_status tlb_init_fields(tlb_ctx* c, const double* c1, const double* c2, const double* ux,
+                           const double* uy) {
+    if (!c || !c1 || !c2) return fail(c, TLB_EINVAL, "null pointer");
+    if (!c->geometry) return fail(c, TLB_ESTATE, "set_geometry must precede init_fields");
+    const size_t n = size_t(c->nx) * c->ny;
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(c1[i]) || !std::isfinite(c2[i]) || (ux && !std::isfinite(ux[i])) ||
+            (uy && !std::isfinite(uy[i])))
+            return fail(c, TLB_EINVAL, "non-finite initial field");
+    std::vector<double> host(4 * n, 0.0);
+    std::memcpy(host.data(), c1, n * sizeof(double));
+    std::memcpy(host.data() + n, c2, n * sizeof(double));
+    if (ux) std::memcpy(host.data() + 2 * n, ux, n * sizeof(double));
+    if (uy) std::memcpy(host.data() + 3 * n, uy, n * sizeof(double));
+    // FP16 storage scale per family: a power of two that maps the largest
+    // initial moving population (bounded by the velocity and mu ranges) well
+    // inside the FP16 range, with 2^6 headroom for transients.
+    if (c->prec == P16) {
+        double umax = 0.0;
+        for (size_t i = 0; i < n; ++i) {
+            double u2 = (ux ? ux[i] * ux[i] : 0.0) + (uy ? uy[i] * uy[i] : 0.0);
+            umax = std::fmax(umax, std::sqrt(u2));
+        }
+        const double m = std::fmax(umax, 0.02);
+        const double rmax = std::fmax(c->fl.rho[0], std::fmax(c->fl.rho[1], c->fl.rho[2]));
+        const double fmaxv[3] = {m + 1e-2, m + 1e-2, rmax * m + 1e-2};
+        for (int f = 0; f < 3; ++f) {
+            int ex = int(std::floor(std::log2(1024.0 / fmaxv[f])));
+            c->c32.scale[f] = std::ldexp(1.0f, ex);
+            c->c32.iscale[f] = std::ldexp(1.0f, -ex);
+        }
+    }
+    double* stage = reinterpret_cast<double*>(c->ws + c->L.off_stage);
+    hipError_t e = hipMemcpyAsync(stage, host.data(), 4 * n * sizeof(double), hipMemcpyHostToDevice,
+                                  c->stream);
+    if (e != hipSuccess) return dev_fail(c, e, "init upload");
+    Grid g = c->grid;
+    e = launch_init(c->prec, g, consts_ptr(c), reinterpret_cast<uint8_t*>(c->ws + c->L.off_mat),
+                    reinterpret_cast<double*>(c->ws + c->L.off_mtab), stage, popbuf(c, 0),
+                    c->ws + c->L.off_hist, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return dev_fail(c, e, "init kernel");
+    c->cur = 0;
+    c->steps = 0;
+    c->since_check = 0;
+    c->inited = true;
+    c->diverged = false;
+    c->health_pending = false;
+    return TLB_OK;
+}
+
+static tlb_status step_impl(tlb_ctx* c, int64_t nsteps, bool checks) {
+    for (int64_t s = 0; s < nsteps; ++s) {
+        hipError_t e = launch_step(c->prec, c->grid, consts_ptr(c),
+                                   reinterpret_cast<uint8_t*>(c->ws + c->L.off_mat),
+                                   reinterpret_cast<double*>(c->ws + c->L.off_mtab),
+                                   popbuf(c, c->cur), popbuf(c, 1 - c->cur), c->ws + c->L.off_hist,
+                                   c->stream);
+        if (e != hipSuccess) return dev_fail(c, e, "step kernel");
+        c->cur = 1 - c->cur;
+        ++c->steps;
+        if (checks && c->check_interval > 0 && ++c->since_check >= c->check_interval) {
+            c->since_check = 0;
+            tlb_status st = run_mass(c);
+            if (st != TLB_OK) return st;
+            e = hipMemcpyAsync(c->health, c->ws + c->L.off_result, 4 * sizeof(double),
+                               hipMemcpyDeviceToHost, c->stream);
+            if (e != hipSuccess) return dev_fail(c, e, "health copy");
+            c->health_pending = true;
+        }
+    }
+    return TLB_OK;
+}
+
+tlb_status tlb_step(tlb_ctx* c, int64_t nsteps) {
+    if (!c || nsteps < 0) return fail(c, TLB_EINVAL, "null context or negative step count");
+    if (!c->inited) return fail(c, TLB_ESTATE, "init_fields must precede step");
+    poll_health(c);
+    if (c->diverged) return fail(c, TLB_EDIVERGED, "NaN/Inf order parameter detected");
+    return step_impl(c, nsteps, true);
+}
+
+tlb_status tlb_set_check_interval(tlb_ctx* c, int64_t interval) {
+    if (!c || interval < 0) return fail(c, TLB_EINVAL, "bad interval");
+    c->check_interval = interval;
+    c->since_check = 0;
+    return TLB_OK;
+}
+
+int64_t tlb_step_count(const tlb_ctx* c) { return c ? c->steps : -1; }
+
+tlb_status tlb_set_tile_rows(tlb_ctx* c, int rows) {
+    if (!c || (rows != 2 && rows != 4 && rows != 8 && rows != 16))
+        return fail(c, TLB_EINVAL, "tile rows must be 2, 4, 8 or 16");
+    set_grid(c, rows);
+    return TLB_OK;
+}
+
+tlb_status tlb_read_fields(tlb_ctx* c, uint32_t mask, double* out) {
+    if (!c || !out) return fail(c, TLB_EINVAL, "null pointer");
+    if (mask == 0 || (mask & ~uint32_t(TLB_F_ALL))) return fail(c, TLB_EINVAL, "bad field mask");
+    if (!c->inited) return fail(c, TLB_ESTATE, "init_fields must precede read_fields");
+    const size_t n = size_t(c->nx) * c->ny;
+    double* stage = reinterpret_cast<double*>(c->ws + c->L.off_stage);
+    hipError_t e = launch_readout(c->prec, c->grid, consts_ptr(c),
+                                  reinterpret_cast<uint8_t*>(c->ws + c->L.off_mat),
+                                  reinterpret_cast<double*>(c->ws + c->L.off_mtab), popbuf(c, c->cur),
+                                  c->ws + c->L.off_hist, stage, c->stream);
+    if (e != hipSuccess) return dev_fail(c, e, "readout kernel");
+    int o = 0;
+    for (int f = 0; f < 10; ++f) {
+        if (!(mask & (1u << f))) continue;
+        e = hipMemcpyAsync(out + size_t(o) * n, stage + size_t(f) * n, n * sizeof(double),
+                           hipMemcpyDeviceToHost, c->stream);
+        if (e != hipSuccess) return dev_fail(c, e, "readout copy");
+        ++o;
+    }
+    e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return dev_fail(c, e, "readout sync");
+    return TLB_OK;
+}
+
+tlb_status tlb_read_populations(tlb_ctx* c, double* out) {
+    if (!c || !out) return fail(c, TLB_EINVAL, "null pointer");
+    if (!c->inited) return fail(c, TLB_ESTATE, "init_fields must precede read_populations");
+    const size_t n = size_t(c->nx) * c->ny;
+    double* stage = reinterpret_cast<double*>(c->ws + c->L.off_stage);
+    hipError_t e = launch_populations(c->prec, c->grid, consts_ptr(c),
+                                      reinterpret_cast<uint8_t*>(c->ws + c->L.off_mat),
+                                      popbuf(c, c->cur), stage, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out, stage, 27 * n * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return dev_fail(c, e, "read_populations");
+    return TLB_OK;
+}
+
+tlb_status tlb_mass(tlb_ctx* c, double out[3]) {
+    if (!c || !out) return fail(c, TLB_EINVAL, "null pointer");
+    if (!c->inited) return fail(c, TLB_ESTATE, "init_fields must precede mass");
+    tlb_status st = run_mass(c);
+    if (st != TLB_OK) return st;
+    double r[4];
+    hipError_t e = hipMemcpyAsync(r, c->ws + c->L.off_result, sizeof(r), hipMemcpyDeviceToHost,
+                                  c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return dev_fail(c, e, "mass copy");
+    out[0] = r[0];
+    out[1] = r[1];
+    out[2] = r[2];
+    if (r[3] != 0.0) {
+        c->diverged = true;
+        return fail(c, TLB_EDIVERGED, "NaN/Inf order parameter detected");
+    }
+    return TLB_OK;
+}
+
+tlb_status tlb_checkpoint_bytes(const tlb_ctx* c, size_t* bytes) {
+    if (!c || !bytes) return TLB_EINVAL;
+    *bytes = 64 + c->L.pop_bytes + c->L.hist_bytes;
+    return TLB_OK;
+}
+
+tlb_status tlb_checkpoint_save(tlb_ctx* c, void* buf) {
+    if (!c || !buf) return fail(c, TLB_EINVAL, "null pointer");
+    if (!c->inited) return fail(c, TLB_ESTATE, "nothing to save before init_fields");
+    char* b = static_cast<char*>(buf);
+    std::memset(b, 0, 64);
+    std::memcpy(b, "TLBCKPT1", 8);
+    int32_t hdr[4] = {c->nx, c->ny, c->prec, 0};
+    std::memcpy(b + 8, hdr, sizeof(hdr));
+    std::memcpy(b + 24, &c->steps, 8);
+    std::memcpy(b + 32, c->c32.scale, 3 * sizeof(float));
+    std::memcpy(b + 44, c->c32.iscale, 3 * sizeof(float));
+    hipError_t e = hipMemcpyAsync(b + 64, c->ws + c->L.off_pop[c->cur], c->L.pop_bytes,
+                                  hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b + 64 + c->L.pop_bytes, c->ws + c->L.off_hist, c->L.hist_bytes,
+                           hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return dev_fail(c, e, "checkpoint save");
+    return TLB_OK;
+}
+
+tlb_status tlb_checkpoint_load(tlb_ctx* c, const void* buf) {
+    if (!c || !buf) return fail(c, TLB_EINVAL, "null pointer");
+    if (!c->geometry) return fail(c, TLB_ESTATE, "set_geometry must precede checkpoint_load");
+    const char* b = static_cast<const char*>(buf);
+    int32_t hdr[4];
+    std::memcpy(hdr, b + 8, sizeof(hdr));
+    if (std::memcmp(b, "TLBCKPT1", 8) || hdr[0] != c->nx || hdr[1] != c->ny || hdr[2] != c->prec)
+        return fail(c, TLB_EINVAL, "checkpoint does not match this context");
+    int64_t steps;
+    std::memcpy(&steps, b + 24, 8);
+    hipError_t e = hipMemcpyAsync(c->ws + c->L.off_pop[0], b + 64, c->L.pop_bytes,
+                                  hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->ws + c->L.off_hist, b + 64 + c->L.pop_bytes, c->L.hist_bytes,
+                           hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return dev_fail(c, e, "checkpoint load");
+    std::memcpy(c->c32.scale, b + 32, 3 * sizeof(float));
+    std::memcpy(c->c32.iscale, b + 44, 3 * sizeof(float));
+    c->cur = 0;
+    c->steps = steps;
+    c->since_check = 0;
+    c->inited = true;
+    c->diverged = false;
+    c->health_pending = false;
+    return TLB_OK;
+}
+
+tlb_status tlb_time_steps(tlb_ctx* c, int64_t nsteps, double* ms) {
+    if (!c || !ms || nsteps <= 0) return fail(c, TLB_EINVAL, "bad arguments");
+    if (!c->inited) return fail(c, TLB_ESTATE, "init_fields must precede time_steps");
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+        return fail(c, TLB_EDEVICE, "event create");
+    hipEventRecord(a, c->stream);
+    tlb_status st = step_impl(c, nsteps, false);
+    hipEventRecord(b, c->stream);
+    hipError_t e = hipEventSynchronize(b);
+    float t = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    if (st != TLB_OK) return st;
+    if (e != hipSuccess) return dev_fail(c, e, "time_steps");
+    *ms = double(t) / double(nsteps);
+    return TLB_OK;
+}
+
+const char* tlb_last_error(const tlb_ctx* c) {
+    if (c) return c->err.c_str();
+    return g_last_error.c_str();
+}
+
+void tlb_destroy(tlb_ctx* c) {
+    if (!c) return;
+    if (c->stream) hipStreamSynchronize(c->stream);
+    else hipDeviceSynchronize();
+    if (c->health) hipHostFree(c->health);
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,72 @@
+// tlb_internal.h -- structures shared by the host runtime and the gfx950
+// kernels of the ternary wetting lattice Boltzmann library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace tlb {
+
+constexpr int kMaxMaterials = 15;
+constexpr int kTileX = 64;        // interior columns per workgroup (one wave64 row)
+constexpr int kThreads = 256;     // four wave64s per workgroup
+constexpr int kReduceBlocks = 512;
+
+enum Precision : int { P64 = 0, P32 = 1, P16 = 2 };
+
+// Device views of the state.  Populations are stored SoA as 27 planes
+// q = fam*9 + k (fam 0: f^1, 1: f^2, 2: g), each plane npad elements with
+// row pitch `pitch`.  In P16 mode the rest planes q = 0 and q = 9 live in
+// the float array `rest` (two planes) and all other planes are FP16 values
+// multiplied by scale[fam].
+struct PopBuf {
+    void* planes;   // element type: double (P64), float (P32), _Float16 (P16)
+    float* rest;    // P16 only
+};
+
+// Constants of one solve, precomputed on the host in FP64 and rounded to
+// the arithmetic type of the kernel.
+template <typename R>
+struct Consts {
+    R drho1, drho2, rho3;        // rho = rho3 + (rho1-rho3) c1 + (rho2-rho3) c2 (Eq. 14)
+    R dnu1, dnu2, nu3;           // Eq. 15
+    R itau1, itau2;              // 1/tau_i
+    R fs1, fs2;                  // 1 - 1/(2 tau_i) (Eq. 11a)
+    R eta1, eta2;                // Eq. 18a per component
+    R am1, am2;                  // (rho_i - rho_3) M_i (Eq. 12)
+    R lam1, lam2, lam3, lamT;    // Eqs. 7, 9
+    R k12D, k34D, k4D;           // 12/D, 3D/4, 4/D
+    R gx, gy;                    // gravity
+    float scale[3], iscale[3];   // P16 storage scales per family
+};
+
+// Per-material table (device memory, FP64): for material id m in 0..15 the
+// five values cos(theta12), cos(theta13), cos(theta23), u_wall_x, u_wall_y at
+// mtab[5*m .. 5*m+4]; id 0 (fluid) is all zero.
+constexpr int kMatStride = 5;
+
+struct Grid {
+    int nx, ny, pitch;
+    long npad;                   // ny * pitch
+    int tiles_x, tiles_y, tile_rows;
+};
+
+// host-side launchers (tlb_kernels.hip)
+// `consts` points to a host Consts<double> (P64) or Consts<float> (P32, P16);
+// `mtab` to the device material table.
+hipError_t launch_step(int prec, const Grid& g, const void* consts, const uint8_t* mat,
+                       const double* mtab, PopBuf src, PopBuf dst, void* hist,
+                       hipStream_t s);
+hipError_t launch_init(int prec, const Grid& g, const void* consts, const uint8_t* mat,
+                       const double* mtab, const double* in4, PopBuf dst, void* hist,
+                       hipStream_t s);
+hipError_t launch_readout(int prec, const Grid& g, const void* consts, const uint8_t* mat,
+                          const double* mtab, PopBuf src, void* hist, double* out10,
+                          hipStream_t s);
+hipError_t launch_populations(int prec, const Grid& g, const void* consts,
+                              const uint8_t* mat, PopBuf src, double* out27, hipStream_t s);
+hipError_t launch_mass(int prec, const Grid& g, const void* consts, const uint8_t* mat,
+                       PopBuf src, double* partials, double* result, hipStream_t s);
+
+}  // namespace tlb

@@ -1,0 +1,227 @@
+"""ctypes binding of ``libtlb.so`` (C ABI in include/tlb.h).
+
+Argument marshalling only: every step of the solver runs in the HIP
+library.  PyTorch provides the device workspace and the stream.  Importing
+this module raises if the library has not been built -- there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch  # noqa: F401  (loads the HIP runtime before libtlb binds to it)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtlb.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libtlb.so is not built: run python -m paper_1710_09534_amd.build")
+
+TLB_OK, TLB_EINVAL, TLB_EPARAM, TLB_ENOMEM, TLB_EDEVICE, TLB_EDIVERGED, TLB_ESTATE, TLB_EBUSY = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+TLB_FP64, TLB_FP32, TLB_FP16DEV = 0, 1, 2
+PRECISIONS = {"fp64": TLB_FP64, "fp32": TLB_FP32, "fp16dev": TLB_FP16DEV}
+FIELDS = ("c1", "c2", "c3", "rho", "ux", "uy", "p", "mu1", "mu2", "mu3")
+F_ALL = (1 << len(FIELDS)) - 1
+
+
+class TlbError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("tlb status %d: %s" % (status, msg))
+        self.status = status
+
+
+class tlb_fluid(C.Structure):
+    _fields_ = [("sigma12", C.c_double), ("sigma13", C.c_double), ("sigma23", C.c_double),
+                ("D", C.c_double), ("M0", C.c_double), ("tau1", C.c_double),
+                ("tau2", C.c_double), ("rho", C.c_double * 3), ("nu", C.c_double * 3),
+                ("gravity", C.c_double * 2)]
+
+
+class tlb_material(C.Structure):
+    _fields_ = [("theta13_deg", C.c_double), ("theta23_deg", C.c_double),
+                ("wall_u", C.c_double * 2)]
+
+
+lib = C.CDLL(LIB_PATH)
+_vp = C.c_void_p
+_D = C.POINTER(C.c_double)
+_SIGS = {
+    "tlb_workspace_bytes": (C.c_size_t, [C.c_int, C.c_int, C.c_int]),
+    "tlb_create": (C.c_int, [C.c_int, C.c_int, C.c_int, C.POINTER(tlb_fluid), _vp, C.c_size_t,
+                             _vp, C.POINTER(_vp)]),
+    "tlb_set_geometry": (C.c_int, [_vp, C.c_int, C.c_int, C.POINTER(C.c_uint8),
+                                   C.POINTER(tlb_material), C.c_int, _D]),
+    "tlb_init_fields": (C.c_int, [_vp, _D, _D, _D, _D]),
+    "tlb_step": (C.c_int, [_vp, C.c_int64]),
+    "tlb_set_check_interval": (C.c_int, [_vp, C.c_int64]),
+    "tlb_step_count": (C.c_int64, [_vp]),
+    "tlb_read_fields": (C.c_int, [_vp, C.c_uint32, _D]),
+    "tlb_read_populations": (C.c_int, [_vp, _D]),
+    "tlb_mass": (C.c_int, [_vp, _D]),
+    "tlb_checkpoint_bytes": (C.c_int, [_vp, C.POINTER(C.c_size_t)]),
+    "tlb_checkpoint_save": (C.c_int, [_vp, _vp]),
+    "tlb_checkpoint_load": (C.c_int, [_vp, _vp]),
+    "tlb_time_steps": (C.c_int, [_vp, C.c_int64, _D]),
+    "tlb_set_tile_rows": (C.c_int, [_vp, C.c_int]),
+    "tlb_last_error": (C.c_char_p, [_vp]),
+    "tlb_destroy": (None, [_vp]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _fn = getattr(lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+
+def tlb_last_error(ctx=None) -> str:
+    return lib.tlb_last_error(ctx).decode()
+
+
+def _check(status, ctx=None):
+    if status != TLB_OK:
+        raise TlbError(status, tlb_last_error(ctx))
+
+
+def _dp(a):
+    return a.ctypes.data_as(_D) if a is not None else None
+
+
+def make_fluid(fl: dict) -> tlb_fluid:
+    f = tlb_fluid()
+    f.sigma12, f.sigma13, f.sigma23 = fl["sigma12"], fl["sigma13"], fl["sigma23"]
+    f.D, f.M0, f.tau1, f.tau2 = fl["D"], fl["M0"], fl["tau1"], fl["tau2"]
+    for i in range(3):
+        f.rho[i] = fl["rho"][i]
+        f.nu[i] = fl["nu"][i]
+    g = fl.get("gravity", (0.0, 0.0))
+    f.gravity[0], f.gravity[1] = g[0], g[1]
+    return f
+
+
+def make_materials(mats):
+    arr = (tlb_material * max(1, len(mats)))()
+    for i, m in enumerate(mats):
+        arr[i].theta13_deg = m["theta13"]
+        arr[i].theta23_deg = m["theta23"]
+        wu = m.get("wall_u", (0.0, 0.0))
+        arr[i].wall_u[0], arr[i].wall_u[1] = wu[0], wu[1]
+    return arr
+
+
+def tlb_workspace_bytes(nx: int, ny: int, precision: int) -> int:
+    return int(lib.tlb_workspace_bytes(nx, ny, precision))
+
+
+class Solver:
+    """One lattice on the current HIP device: owns a torch workspace and the
+    C context.  Method names follow the C ABI (tlb_<name>)."""
+
+    def __init__(self, nx, ny, fluid: dict, precision="fp64", device="cuda:0", stream=None):
+        import torch
+        self.nx, self.ny = int(nx), int(ny)
+        self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        self.device = torch.device(device)
+        nbytes = tlb_workspace_bytes(self.nx, self.ny, self.precision)
+        if nbytes == 0:
+            raise TlbError(TLB_EINVAL, "bad lattice size")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._fluid = make_fluid(fluid)
+        h = _vp()
+        st = lib.tlb_create(self.nx, self.ny, self.precision, C.byref(self._fluid),
+                            _vp(self.workspace.data_ptr()), nbytes,
+                            _vp(self.stream.cuda_stream), C.byref(h))
+        _check(st, None)
+        self.ctx = h
+
+    def __del__(self):
+        self.destroy()
+
+    def destroy(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx is not None and ctx.value:
+            lib.tlb_destroy(ctx)
+        self.ctx = None
+
+    @property
+    def n(self):
+        return self.nx * self.ny
+
+    def _f(self, a):
+        if a is None:
+            return None
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        if a.shape != (self.ny, self.nx):
+            raise ValueError("field shape %s != %s" % (a.shape, (self.ny, self.nx)))
+        return a
+
+    def set_geometry(self, material, mats, periodic=(1, 1)):
+        material = np.ascontiguousarray(material, dtype=np.uint8)
+        if material.shape != (self.ny, self.nx):
+            raise ValueError("material shape mismatch")
+        arr = make_materials(mats)
+        th12 = np.zeros(max(1, len(mats)))
+        st = lib.tlb_set_geometry(self.ctx, int(periodic[0]), int(periodic[1]),
+                                  material.ctypes.data_as(C.POINTER(C.c_uint8)), arr, len(mats),
+                                  _dp(th12))
+        _check(st, self.ctx)
+        return th12[:len(mats)]
+
+    def init_fields(self, c1, c2, ux=None, uy=None):
+        c1, c2, ux, uy = (self._f(a) for a in (c1, c2, ux, uy))
+        _check(lib.tlb_init_fields(self.ctx, _dp(c1), _dp(c2), _dp(ux), _dp(uy)), self.ctx)
+
+    def step(self, n: int = 1):
+        _check(lib.tlb_step(self.ctx, int(n)), self.ctx)
+
+    def set_check_interval(self, n: int):
+        _check(lib.tlb_set_check_interval(self.ctx, int(n)), self.ctx)
+
+    def set_tile_rows(self, rows: int):
+        _check(lib.tlb_set_tile_rows(self.ctx, int(rows)), self.ctx)
+
+    @property
+    def step_count(self) -> int:
+        return int(lib.tlb_step_count(self.ctx))
+
+    def read_fields(self, mask: int = F_ALL) -> dict:
+        names = [f for i, f in enumerate(FIELDS) if mask & (1 << i)]
+        out = np.zeros((len(names), self.ny, self.nx))
+        _check(lib.tlb_read_fields(self.ctx, mask, _dp(out)), self.ctx)
+        return {k: out[i] for i, k in enumerate(names)}
+
+    def read_populations(self) -> np.ndarray:
+        out = np.zeros((27, self.ny, self.nx))
+        _check(lib.tlb_read_populations(self.ctx, _dp(out)), self.ctx)
+        return out
+
+    def mass(self) -> np.ndarray:
+        out = np.zeros(3)
+        _check(lib.tlb_mass(self.ctx, _dp(out)), self.ctx)
+        return out
+
+    def checkpoint_save(self) -> bytes:
+        n = C.c_size_t()
+        _check(lib.tlb_checkpoint_bytes(self.ctx, C.byref(n)), self.ctx)
+        buf = C.create_string_buffer(n.value)
+        _check(lib.tlb_checkpoint_save(self.ctx, buf), self.ctx)
+        return buf.raw
+
+    def checkpoint_load(self, blob: bytes):
+        buf = C.create_string_buffer(blob, len(blob))
+        _check(lib.tlb_checkpoint_load(self.ctx, buf), self.ctx)
+
+    def time_steps(self, n: int) -> float:
+        ms = C.c_double()
+        _check(lib.tlb_time_steps(self.ctx, int(n), C.byref(ms)), self.ctx)
+        return ms.value
+
+
+def from_problem(problem: dict, precision="fp64", device="cuda:0", init=True) -> Solver:
+    """Creates a solver for a problem dict of ``workloads`` and initialises it."""
+    s = Solver(problem["nx"], problem["ny"], problem["fluid"], precision, device)
+    s.set_geometry(problem["material"], problem["mats"], problem.get("periodic", (1, 1)))
+    if init:
+        s.init_fields(problem["c1"], problem["c2"], problem.get("ux"), problem.get("uy"))
+    return s

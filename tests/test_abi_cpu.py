@@ -1,0 +1,107 @@
+"""Host-side checks of the C-ABI library that need no GPU: it loads, exports
+every symbol include/tlb.h declares, sizes workspaces, and rejects invalid
+input before touching the device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tlb.h")
+LIB = os.path.join(ROOT, "paper_1710_09534_amd", "libtlb.so")
+
+
+def declared_symbols():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tlb_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        import paper_1710_09534_amd.build as b
+        b.build()
+    return C.CDLL(LIB)
+
+
+def test_exports_every_declared_symbol(lib):
+    syms = declared_symbols()
+    assert len(syms) >= 15
+    for s in syms:
+        assert hasattr(lib, s), s
+
+
+def test_binding_names_match_header():
+    from paper_1710_09534_amd import tlb
+    for s in declared_symbols():
+        assert s in tlb._SIGS or s.startswith("tlb_server"), s
+
+
+def test_workspace_sizes():
+    from paper_1710_09534_amd import tlb
+    b64 = tlb.tlb_workspace_bytes(1024, 2048, tlb.TLB_FP64)
+    b32 = tlb.tlb_workspace_bytes(1024, 2048, tlb.TLB_FP32)
+    b16 = tlb.tlb_workspace_bytes(1024, 2048, tlb.TLB_FP16DEV)
+    n = 1024 * 2048
+    # two lattices of 27 planes + 4 history planes + staging
+    assert b64 >= n * (2 * 27 * 8 + 4 * 8)
+    assert b32 >= n * (2 * 27 * 4 + 4 * 4)
+    assert b16 >= n * (2 * (25 * 2 + 2 * 4) + 4 * 4)
+    assert b64 > b32 > b16 > 0
+    assert tlb.tlb_workspace_bytes(2, 10, tlb.TLB_FP64) == 0
+    assert tlb.tlb_workspace_bytes(10, 10, 7) == 0
+
+
+def _fl(**kw):
+    from paper_1710_09534_amd import workloads as W
+    fl = W.fluid()
+    fl.update(kw)
+    return fl
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(tau1=0.5), -2),
+    (dict(sigma12=5e-3), -2),             # lambda_3 < 0
+    (dict(sigma12=1.9e-3, sigma13=1e-3, sigma23=1e-3), -2),  # lambda_3 <= lambda_T/2
+    (dict(D=0.0), -2),
+    (dict(M0=-1.0), -2),
+    (dict(rho=[1.0, 0.0, 1.0]), -2),
+])
+def test_create_rejects_inadmissible_parameters(kw, code):
+    from paper_1710_09534_amd import tlb
+    f = tlb.make_fluid(_fl(**kw))
+    h = C.c_void_p()
+    ws = C.c_void_p(1 << 20)  # never dereferenced: validation fails first
+    st = tlb.lib.tlb_create(64, 64, 0, C.byref(f), ws, 1 << 40, None, C.byref(h))
+    assert st == code and not h.value
+    assert len(tlb.tlb_last_error()) > 0
+
+
+def test_create_rejects_bad_sizes_and_pointers():
+    from paper_1710_09534_amd import tlb
+    f = tlb.make_fluid(_fl())
+    h = C.c_void_p()
+    assert tlb.lib.tlb_create(2, 64, 0, C.byref(f), C.c_void_p(256), 1 << 40, None,
+                              C.byref(h)) == tlb.TLB_EINVAL
+    assert tlb.lib.tlb_create(64, 64, 0, None, C.c_void_p(256), 1 << 40, None,
+                              C.byref(h)) == tlb.TLB_EINVAL
+    assert tlb.lib.tlb_create(64, 64, 0, C.byref(f), None, 1 << 40, None,
+                              C.byref(h)) == tlb.TLB_EINVAL
+    assert tlb.lib.tlb_create(64, 64, 0, C.byref(f), C.c_void_p(257), 1 << 40, None,
+                              C.byref(h)) == tlb.TLB_EINVAL       # misaligned
+    assert tlb.lib.tlb_create(64, 64, 0, C.byref(f), C.c_void_p(256), 1024, None,
+                              C.byref(h)) == tlb.TLB_ENOMEM       # too small
+    assert tlb.lib.tlb_create(64, 64, 9, C.byref(f), C.c_void_p(256), 1 << 40, None,
+                              C.byref(h)) == tlb.TLB_EINVAL
+
+
+def test_null_context_calls_fail_cleanly():
+    from paper_1710_09534_amd import tlb
+    out = np.zeros(3)
+    assert tlb.lib.tlb_step(None, 1) == tlb.TLB_EINVAL
+    assert tlb.lib.tlb_mass(None, tlb._dp(out)) == tlb.TLB_EINVAL
+    assert tlb.lib.tlb_step_count(None) == -1
+    tlb.lib.tlb_destroy(None)

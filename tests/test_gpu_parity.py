@@ -1,0 +1,192 @@
+"""GPU FP64 parity against the FP64 oracle, through the C ABI.
+
+Bar: max-abs difference <= 1e-12 on every macroscopic field (c1, c2, c3,
+rho, u, p, mu_1..3) and on the stored populations, on the paper's workload
+shapes, ragged grids that span several 64-column tiles, every geometry
+kind (channel with moving walls, staircase cylinder, closed box), and at the
+full workload sizes (few steps).  Both sides start from the same seeded
+host arrays.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1710_09534_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+@pytest.fixture(scope="module")
+def tlb():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1710_09534_amd import tlb as t
+    return t
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def run_pair(tlb, p, steps, precision="fp64", rows=None, check_every=None):
+    _say("case %s %dx%d steps=%d %s" % (p["name"], p["nx"], p["ny"], steps, precision))
+    g = tlb.from_problem(p, precision)
+    if rows:
+        g.set_tile_rows(rows)
+    if check_every is not None:
+        g.set_check_interval(check_every)
+    o = oracle.Oracle(p)
+    o.init(p["c1"], p["c2"], p["ux"], p["uy"])
+    if steps:
+        g.step(steps)
+        o.step(steps)
+    return g, o
+
+
+def max_diffs(g, o):
+    fg = g.read_fields()
+    fo = o.fields()
+    return {k: float(np.abs(fg[k] - fo[k]).max()) for k in fo}
+
+
+def assert_parity(g, o, tol=TOL64, pops=True):
+    d = max_diffs(g, o)
+    bad = {k: v for k, v in d.items() if not v <= tol}
+    assert not bad, (bad, d)
+    if pops:
+        pg = g.read_populations()
+        po = o.populations()
+        solid = o.material != 0
+        po[:, solid] = 0.0
+        assert np.abs(pg - po).max() <= tol
+
+
+def test_init_state_matches(tlb):
+    p = W.random_fields(100, 37, geometry="channel", U=0.01, rho=(3.0, 2.0, 1.0))
+    g, o = run_pair(tlb, p, 0)
+    assert_parity(g, o, tol=1e-14)
+
+
+def test_reduction_case_1000_steps(tlb):
+    """The 64x64 reduction-consistency workload (phase-1 drop, phase 2
+    absent), 1000 steps: every field within 1e-12, and f^2 stays zero."""
+    p = W.reduction_case()
+    g, o = run_pair(tlb, p, 1000)
+    assert_parity(g, o)
+    assert np.all(g.read_populations()[9:18] == 0.0)
+
+
+@pytest.mark.parametrize("geometry,nx,ny,U", [
+    ("channel", 100, 37, 0.01), ("cylinder", 130, 70, 0.0), ("box", 70, 50, 0.0),
+    ("periodic", 64, 24, 0.0), ("channel", 200, 9, 0.02)])
+def test_random_three_phase(tlb, geometry, nx, ny, U):
+    p = W.random_fields(nx, ny, geometry=geometry, U=U, rho=(3.0, 2.0, 1.0),
+                        gravity=(0.0, -1e-6))
+    g, o = run_pair(tlb, p, 300)
+    assert_parity(g, o)
+
+
+@pytest.mark.parametrize("rows", [2, 4, 16])
+def test_tile_shape_invariance(tlb, rows):
+    """Results do not depend on the workgroup tile height (bitwise)."""
+    p = W.random_fields(130, 70, geometry="cylinder")
+    a, _ = run_pair(tlb, p, 50, rows=8)
+    b = tlb.from_problem(p)
+    b.set_tile_rows(rows)
+    b.step(50)
+    assert np.array_equal(a.read_populations(), b.read_populations())
+
+
+def test_binary_drops_small(tlb):
+    p = W.binary_drops(seed=3, nx=128, ny=64, R=16)
+    g, o = run_pair(tlb, p, 500)
+    assert_parity(g, o)
+
+
+def test_compound_shear_small(tlb):
+    p = W.compound_shear(seed=1, nx=128, ny=64, R_core=8, R_shell=16)
+    g, o = run_pair(tlb, p, 500)
+    assert_parity(g, o)
+
+
+def test_cylinder_impact_small(tlb):
+    p = W.cylinder_impact(We=50, theta=30, nx=128, ny=256, R_cyl=16, R_shell=12, R_core=6)
+    g, o = run_pair(tlb, p, 300)
+    assert_parity(g, o)
+
+
+@pytest.mark.parametrize("factory,steps", [
+    (lambda: W.binary_drops(seed=0), 20),
+    (lambda: W.compound_shear(seed=0), 10),
+    (lambda: W.cylinder_impact(We=100, theta=150), 3),
+])
+def test_full_size_workloads(tlb, factory, steps):
+    """The 256x128, 512x256 and 1024x2048 workloads at full size, few steps,
+    in the tile shape the benchmark uses."""
+    p = factory()
+    g, o = run_pair(tlb, p, steps)
+    assert_parity(g, o, pops=False)
+
+
+def test_mass_conservation_and_device_sum(tlb):
+    p = W.random_fields(130, 70, geometry="cylinder", rho=(3.0, 2.0, 1.0))
+    g, o = run_pair(tlb, p, 0)
+    m0 = g.mass()
+    assert np.allclose(m0, o.mass(), rtol=1e-13, atol=0)
+    g.step(2000)
+    m1 = g.mass()
+    assert np.all(np.abs(m1 - m0) <= 1e-12 * np.abs(m0))
+
+
+def test_checkpoint_roundtrip_bitwise(tlb):
+    p = W.random_fields(100, 37, geometry="channel", U=0.01)
+    a = tlb.from_problem(p)
+    a.step(40)
+    blob = a.checkpoint_save()
+    a.step(60)
+    b = tlb.from_problem(p, init=False)
+    b.checkpoint_load(blob)
+    assert b.step_count == 40
+    b.step(60)
+    assert np.array_equal(a.read_populations(), b.read_populations())
+
+
+def test_error_paths(tlb):
+    p = W.reduction_case(nx=64, ny=32)
+    s = tlb.Solver(64, 32, p["fluid"])
+    with pytest.raises(tlb.TlbError) as e:
+        s.step(1)
+    assert e.value.status == tlb.TLB_ESTATE
+    bad = p["material"].copy()
+    bad[5, 5] = 9
+    with pytest.raises(tlb.TlbError) as e:
+        s.set_geometry(bad, p["mats"], (1, 0))
+    assert e.value.status == tlb.TLB_EINVAL
+    with pytest.raises(tlb.TlbError) as e:
+        s.set_geometry(p["material"], p["mats"], (0, 0))   # open x edges are fluid
+    assert e.value.status == tlb.TLB_EINVAL
+    with pytest.raises(tlb.TlbError) as e:
+        s.set_geometry(p["material"], [W.material(20, 160), W.material(90, 90)], (1, 0))
+    assert e.value.status == tlb.TLB_EPARAM
+
+
+def test_divergence_is_reported(tlb):
+    """A run driven unstable by an absurd body force is flagged EDIVERGED by
+    the periodic device health check; every kernel still exits normally."""
+    p = W.random_fields(64, 32, geometry="channel", gravity=(0.0, -50.0))
+    g = tlb.from_problem(p)
+    g.set_check_interval(5)
+    with pytest.raises(tlb.TlbError) as e:
+        for _ in range(40):
+            g.step(10)
+            g.mass()
+    assert e.value.status == tlb.TLB_EDIVERGED
+    with pytest.raises(tlb.TlbError):
+        g.step(1)
+    g.read_fields()  # still allowed
