@@ -1,0 +1,204 @@
+"""Benchmark of the fused ternary wetting LB step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32]
+                    [--workload cylinder_impact] [--no-cpu] [--quick]
+
+Workload: the compound-drop / cylinder-impact lattice, 1024 x 2048 nodes,
+staircase cylinder of radius 128 (We = 10, theta = 90 deg), FP32
+populations.  A step is one full pass of the hot path: the fused
+stream/bounce-back/moments/wetting/chemical-potential/force/collision kernel,
+plus the device mass/NaN reduction every 100 steps.  Inputs are resident in
+HBM before timing starts.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor peak
+STORE = {"fp64": (8, 8), "fp32": (4, 4), "fp16dev": (None, 4)}
+COUNTERS = os.path.join(ROOT, "profiles", "step_kernel_counters.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1710_09534_amd", "csrc", "tlb_kernels.hip")
+
+
+def pop_bytes(precision: str) -> float:
+    """Algorithmic bytes per fluid node-step: 27 populations read and
+    written once, 4 history scalars read and written once."""
+    if precision == "fp16dev":
+        pops = 25 * 2 + 2 * 4
+    else:
+        pops = 27 * STORE[precision][0]
+    return 2 * pops + 2 * 4 * STORE[precision][1]
+
+
+def algorithmic_bytes(problem, precision: str) -> float:
+    """Per launch: fluid nodes x per-node bytes + 1 byte of material id per node."""
+    n = problem["nx"] * problem["ny"]
+    fluid = int((problem["material"] == 0).sum())
+    return fluid * pop_bytes(precision) + n * 1.0
+
+
+def kernel_sha() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(precision: str):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it
+    was taken on the current kernel source."""
+    try:
+        d = json.load(open(COUNTERS))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha") != kernel_sha():
+        return None
+    e = d.get("precisions", {}).get(precision)
+    if not e:
+        return None
+    return e.get("traffic_bytes_per_launch")
+
+
+def make_problem(name: str, nx=None, ny=None):
+    from paper_1710_09534_amd import workloads as W
+    if name == "cylinder_impact":
+        return W.cylinder_impact(We=10.0, theta=90.0, **({"nx": nx, "ny": ny} if nx else {}))
+    if name == "sweep":
+        return W.bandwidth_case(nx or 4096, ny or 4096)
+    raise SystemExit("unknown workload %s" % name)
+
+
+def time_precision(tlb, torch, problem, precision, steps, warmup):
+    s = tlb.from_problem(problem, precision)
+    s.set_check_interval(100)
+    s.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    # device time of the step kernel alone (HIP events on the solver's stream)
+    kms = s.time_steps(max(20, steps // 5))
+    m = s.mass()
+    del s
+    return dt, kms, m
+
+
+def cpu_baseline(problem, budget_s=12.0):
+    import oracle
+    o = oracle.Oracle(problem)
+    o.init(problem["c1"], problem["c2"], problem["ux"], problem["uy"])
+    t0 = time.perf_counter()
+    o.step(1)
+    one = time.perf_counter() - t0
+    k = max(1, min(50, int(budget_s / max(one, 1e-3))))
+    t0 = time.perf_counter()
+    o.step(k)
+    dt = time.perf_counter() - t0
+    n = problem["nx"] * problem["ny"]
+    return {"value": round(n * k / dt / 1e6, 3), "unit": "MLUPS", "cores": oracle.Oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "%d steps of the %dx%d workload (after 1 untimed step), FP64 oracle"
+                      % (k, problem["nx"], problem["ny"])}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "fp16dev"])
+    ap.add_argument("--workload", default="cylinder_impact")
+    ap.add_argument("--nx", type=int, default=None)
+    ap.add_argument("--ny", type=int, default=None)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--only", action="store_true", help="time the headline precision only")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB, 10 times (counter scale)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(requested --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if args.copy_calibration:
+        nb = args.copy_calibration << 20
+        a = torch.ones(nb // 4, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(10):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(10):
+            b.copy_(a)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / 10
+        print(json.dumps({"copy_bytes_each_way": nb, "ms": ms,
+                          "gbs_read_plus_write": 2 * nb / (ms * 1e-3) / 1e9}), flush=True)
+        return
+    from paper_1710_09534_amd import tlb
+
+    problem = make_problem(args.workload, args.nx, args.ny)
+    n = problem["nx"] * problem["ny"]
+    fluid = int((problem["material"] == 0).sum())
+    precs = [args.precision] if args.only else ["fp64", "fp32", "fp16dev"]
+    table = {}
+    for prec in precs:
+        dt, kms, m = time_precision(tlb, torch, problem, prec, args.steps, args.warmup)
+        alg = algorithmic_bytes(problem, prec)
+        table[prec] = {
+            "mlups": round(n * args.steps / dt / 1e6, 1),
+            "fluid_mlups": round(fluid * args.steps / dt / 1e6, 1),
+            "ms_per_step": round(dt * 1e3 / args.steps, 5),
+            "kernel_ms": round(kms, 5),
+            "bytes_per_node_step": pop_bytes(prec),
+            "hbm_frac_algorithmic": round(alg / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "mass_final": [float(x) for x in m],
+        }
+        print("# %s: %.1f MLUPS, kernel %.4f ms, %.1f%% of HBM peak (algorithmic)"
+              % (prec, table[prec]["mlups"], kms, 100 * table[prec]["hbm_frac_algorithmic"]),
+              file=sys.stderr, flush=True)
+    head = table[args.precision]
+    alg = algorithmic_bytes(problem, args.precision)
+    achieved = alg / (head["kernel_ms"] * 1e-3) / 1e9
+    traffic = measured_traffic(args.precision)
+    out = {
+        "metric": "MLUPS & %HBM peak per ternary step (FP64 vs FP32/FP16-store); p50/p99 solve latency",
+        "value": head["mlups"],
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "fp16dev": "f16-store/f32"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": "%s %dx%d (compound drop on a staircase cylinder R=128, We=10, "
+                               "theta=90), %s populations"
+                               % (args.workload, problem["nx"], problem["ny"], args.precision),
+                   "nx": problem["nx"], "ny": problem["ny"], "fluid_nodes": fluid,
+                   "precision": args.precision, "check_interval": 100},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "kernel": "step_kernel<%s,8>" % args.precision,
+                     "algorithmic_bytes_per_launch": alg},
+        "precisions": table,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(problem)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

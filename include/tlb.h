@@ -95,6 +95,8 @@ size_t tlb_workspace_bytes(int nx, int ny, tlb_precision p);
  * stream (hipStream_t, NULL = default stream).  Validates the fluid
  * parameters (Eqs. 7, 9, 18): lambda_i > 0 and lambda_i > lambda_T/2,
  * tau_i > 1/2, D > 0, M0 > 0, rho_i > 0, nu_i > 0 (else TLB_EPARAM).
+ * Each family of 9 population planes must stay below 2 GiB (FP64: about
+ * 29.8 M nodes, e.g. 5400 x 5400; else TLB_EINVAL).
  * The library owns *out until tlb_destroy. */
 tlb_status tlb_create(int nx, int ny, tlb_precision p, const tlb_fluid* fl,
                       void* dev_workspace, size_t ws_bytes, void* hip_stream,
@@ -155,8 +157,9 @@ tlb_status tlb_checkpoint_load(tlb_ctx* ctx, const void* host_buf);
  * (HIP events on the context's stream; advances the state by nsteps). */
 tlb_status tlb_time_steps(tlb_ctx* ctx, int64_t nsteps, double* ms_per_step);
 
-/* Kernel tile rows per workgroup (tuning knob; results are identical for
- * every legal value).  rows in {2, 4, 8, 16}. */
+/* Rows of the strip one workgroup of the step kernel marches through
+ * (tuning knob; results are bitwise identical for every legal value).
+ * rows in {16, 32, 64, 128}; default 16. */
 tlb_status tlb_set_tile_rows(tlb_ctx* ctx, int rows);
 
 /* Last error message of ctx, or of the calling thread's last failed

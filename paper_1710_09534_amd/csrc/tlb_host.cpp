@@ -144,7 +144,7 @@ void set_grid(tlb_ctx* c, int rows) {
     c->grid.pitch = c->L.pitch;
     c->grid.npad = long(c->L.npad);
     c->grid.tile_rows = rows;
-    c->grid.tiles_x = (c->nx + kTileX - 1) / kTileX;
+    c->grid.tiles_x = (c->nx + kStripOut - 1) / kStripOut;   // step-kernel strips
     c->grid.tiles_y = (c->ny + rows - 1) / rows;
 }
 
@@ -185,6 +185,11 @@ tlb_status tlb_create(int nx, int ny, tlb_precision p, const tlb_fluid* fl, void
     if (reinterpret_cast<uintptr_t>(dev_workspace) % kAlign)
         return fail(nullptr, TLB_EINVAL, "workspace not 256-byte aligned");
     Layout L = make_layout(nx, ny, int(p));
+    // the step kernel addresses each family of 9 planes (and the history) as
+    // one buffer with 32-bit offsets and discards stores at offset 2^31
+    if (9 * L.npad * elem_bytes(int(p)) >= (size_t(1) << 31) ||
+        4 * L.npad * (p == TLB_FP64 ? 8 : 4) >= (size_t(1) << 31))
+        return fail(nullptr, TLB_EINVAL, "lattice too large: a family of 9 planes must stay below 2 GiB");
     if (ws_bytes < L.total) return fail(nullptr, TLB_ENOMEM, "workspace too small");
     // Eq. 7, Eq. 9
     double lam[3] = {fl->sigma12 + fl->sigma13 - fl->sigma23,
@@ -221,7 +226,7 @@ tlb_status tlb_create(int nx, int ny, tlb_precision p, const tlb_fluid* fl, void
     c->eta[1] = c->M[1] / (cs2 * (fl->tau2 - 0.5));
     fill_consts(c->c64, c);
     fill_consts(c->c32, c);
-    set_grid(c, 8);
+    set_grid(c, 16);
     if (hipHostMalloc(reinterpret_cast<void**>(&c->health), 4 * sizeof(double)) != hipSuccess) {
         delete c;
         return fail(nullptr, TLB_ENOMEM, "pinned health word");
@@ -378,8 +383,8 @@ tlb_status tlb_set_check_interval(tlb_ctx* c, int64_t interval) {
 int64_t tlb_step_count(const tlb_ctx* c) { return c ? c->steps : -1; }
 
 tlb_status tlb_set_tile_rows(tlb_ctx* c, int rows) {
-    if (!c || (rows != 2 && rows != 4 && rows != 8 && rows != 16))
-        return fail(c, TLB_EINVAL, "tile rows must be 2, 4, 8 or 16");
+    if (!c || (rows != 16 && rows != 32 && rows != 64 && rows != 128))
+        return fail(c, TLB_EINVAL, "strip rows must be 16, 32, 64 or 128");
     set_grid(c, rows);
     return TLB_OK;
 }

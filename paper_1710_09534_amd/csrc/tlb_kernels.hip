@@ -10,17 +10,18 @@
 // into slot P_{opp(k)} of that solid node, which only x ever pulls from, so
 // the pull needs no per-link branch.
 //
-// One step is one kernel.  A workgroup owns a 64 x TY tile and
-//   A. pulls f^1, f^2 on the tile plus a 2-node halo and forms c1, c2 in LDS
-//      (Eqs. 3, 13a),
-//   B. forms the chemical potentials on the tile plus a 1-node halo with the
-//      wetting ghosts of Eq. 42 across solid links (Eqs. 8, 20b),
-//   C. per interior node: gradients with the symmetric ghost rule (Eq. 43),
+// One step is one kernel (step_kernel below).  A workgroup marches up a
+// strip of 64 columns, and per group of four rows
+//   A. pulls f^1, f^2 and forms c1, c2 into an LDS ring (Eqs. 3, 13a),
+//   B. forms the chemical potentials with the wetting ghosts of Eq. 42
+//      across solid links (Eqs. 8, 20b),
+//   C. per node: gradients with the symmetric ghost rule (Eq. 43),
 //      surface-tension force, velocity, interfacial force, pressure,
 //      Euler time derivative, equilibria, sources and BGK collision
 //      (Eqs. 2, 4, 11-15, 18b, 19, 45), and the coalesced stores.
 // Workgroup ids are remapped so that each of the eight XCDs walks one
-// contiguous band of tiles: halo re-reads then hit that XCD's L2.
+// contiguous band of strips: side-halo re-reads then hit that XCD's L2.
+// The init and readout kernels use a plain 64 x 8 tile with a 2-node halo.
 #include <hip/hip_runtime.h>
 
 #include "tlb_internal.h"
@@ -166,86 +167,44 @@ __device__ __forceinline__ void phase_a(Smem<P, TY>& sm, const Grid& g,
     }
 }
 
-// Phase B: chemical potentials (Eq. 8) on the mu region; the Laplacian of
-// c_i (Eq. 20b) sees, across a link into a solid node of material m, the
-// ghost c_i + (4/D) h_i(c) of Eq. 42 evaluated at the fluid node itself.
-template <int P, int TY>
-__device__ __forceinline__ void phase_b(Smem<P, TY>& sm, const Consts<typename Tr<P>::R>& c) {
-    using R = typename Tr<P>::R;
-    using SM = Smem<P, TY>;
-    for (int i = threadIdx.x; i < SM::MH * SM::MW; i += kThreads) {
-        int my = i / SM::MW;
-        int mx = i - my * SM::MW;
-        int ci = (my + 1) * SM::CW + mx + 1;
-        R mu1 = R(0), mu2 = R(0), mu3 = R(0);
-        if (sm.m[ci] == 0) {
-            R c1 = sm.c1[ci], c2 = sm.c2[ci];
-            R c3 = R(1) - c1 - c2;
-            R l1 = R(0), l2 = R(0), l3 = R(0);
-#pragma unroll
-            for (int k = 1; k < 9; ++k) {
-                int ni = ci + EY[k] * SM::CW + EX[k];
-                int mn = sm.m[ni];
-                R n1, n2, n3;
-                if (mn) {
-                    const R* t = &sm.mt[kMatStride * mn];
-                    R h1 = t[1] * c1 * c3 + t[0] * c1 * c2;
-                    R h2 = -t[0] * c1 * c2 + t[2] * c2 * c3;
-                    R h3 = -t[2] * c2 * c3 - t[1] * c1 * c3;
-                    n1 = c1 + c.k4D * h1;
-                    n2 = c2 + c.k4D * h2;
-                    n3 = c3 + c.k4D * h3;
-                } else {
-                    n1 = sm.c1[ni];
-                    n2 = sm.c2[ni];
-                    n3 = R(1) - n1 - n2;
-                }
-                l1 += wgt<R>(k) * (n1 - c1);
-                l2 += wgt<R>(k) * (n2 - c2);
-                l3 += wgt<R>(k) * (n3 - c3);
-            }
-            l1 *= R(6);  // 2 / c_s^2
-            l2 *= R(6);
-            l3 *= R(6);
-            R tri = R(2) * c.lamT * c1 * c2 * (R(1) - c1 - c2);
-            mu1 = c.k12D * (c.lam1 * c1 * (R(1) - c1) * (R(1) - R(2) * c1) - tri) - c.k34D * c.lam1 * l1;
-            mu2 = c.k12D * (c.lam2 * c2 * (R(1) - c2) * (R(1) - R(2) * c2) - tri) - c.k34D * c.lam2 * l2;
-            mu3 = c.k12D * (c.lam3 * c3 * (R(1) - c3) * (R(1) - R(2) * c3) - tri) - c.k34D * c.lam3 * l3;
-        }
-        sm.mu1[i] = mu1;
-        sm.mu2[i] = mu2;
-        sm.mu3[i] = mu3;
-    }
-}
-
 // Macroscopic state of one interior node (phase C front half).
 template <typename R>
 struct NodeMacro {
     R c1, c2, rho, itg, mu1, mu2, ux, uy, p, grx, gry, fx, fy, fax, fay;
 };
 
+// LDS neighbourhood of one node: row pointers for y-1, y, y+1 (index 0..2),
+// each already offset to the node's column.
+template <typename R>
+struct Stencil {
+    const R* c1[3];
+    const R* c2[3];
+    const uint8_t* m[3];
+    const R* mu1[3];
+    const R* mu2[3];
+    R mu3;
+};
+
 // Gradients (Eq. 20a, symmetric ghosts of Eq. 43), forces, velocity
 // (Eq. 13b), interfacial force (Eq. 12) and pressure (Eq. 13c) from the
 // pulled g and the LDS fields.
-template <int P, int TY>
-__device__ __forceinline__ NodeMacro<typename Tr<P>::R> node_macro(
-    const Smem<P, TY>& sm, const Consts<typename Tr<P>::R>& c, int ci, int mi,
-    const typename Tr<P>::R* gg) {
-    using R = typename Tr<P>::R;
-    using SM = Smem<P, TY>;
+// `mask` (bit k-1 set when the neighbour along e_k is solid) replaces the
+// LDS material bytes when MASK is true.
+template <typename R, bool MASK = false>
+__device__ __forceinline__ NodeMacro<R> node_macro(const Stencil<R>& s, const Consts<R>& c,
+                                                   const R* gg, unsigned mask = 0u) {
     NodeMacro<R> o;
-    R c1 = sm.c1[ci], c2 = sm.c2[ci];
-    R mu1 = sm.mu1[mi], mu2 = sm.mu2[mi], mu3 = sm.mu3[mi];
+    const R c1 = s.c1[1][0], c2 = s.c2[1][0];
+    const R mu1 = s.mu1[1][0], mu2 = s.mu2[1][0], mu3 = s.mu3;
     R g1x = R(0), g1y = R(0), g2x = R(0), g2y = R(0), lm1 = R(0), lm2 = R(0);
 #pragma unroll
     for (int k = 1; k < 9; ++k) {
-        int ni = ci + EY[k] * SM::CW + EX[k];
-        int nmi = mi + EY[k] * SM::MW + EX[k];
-        bool solid = sm.m[ni] != 0;
-        R v1 = solid ? c1 : sm.c1[ni];
-        R v2 = solid ? c2 : sm.c2[ni];
-        R w1 = solid ? mu1 : sm.mu1[nmi];
-        R w2 = solid ? mu2 : sm.mu2[nmi];
+        const int r = EY[k] + 1;
+        const bool solid = MASK ? ((mask >> (k - 1)) & 1u) != 0u : s.m[r][EX[k]] != 0;
+        const R v1 = solid ? c1 : s.c1[r][EX[k]];
+        const R v2 = solid ? c2 : s.c2[r][EX[k]];
+        const R w1 = solid ? mu1 : s.mu1[r][EX[k]];
+        const R w2 = solid ? mu2 : s.mu2[r][EX[k]];
         if (EX[k]) {
             g1x += wgt<R>(k) * R(EX[k]) * v1;
             g2x += wgt<R>(k) * R(EX[k]) * v2;
@@ -259,16 +218,16 @@ __device__ __forceinline__ NodeMacro<typename Tr<P>::R> node_macro(
     }
     g1x *= R(3); g1y *= R(3); g2x *= R(3); g2y *= R(3);   // 1 / c_s^2
     lm1 *= R(6); lm2 *= R(6);
-    R g3x = -(g1x + g2x), g3y = -(g1y + g2y);              // c3 = 1 - c1 - c2
-    R rho = c.rho3 + c.drho1 * c1 + c.drho2 * c2;          // Eq. 14
-    R nu = c.nu3 + c.dnu1 * c1 + c.dnu2 * c2;              // Eq. 15
-    R taug = R(3) * nu + R(0.5);                           // Eq. 18b
-    R grx = c.drho1 * g1x + c.drho2 * g2x;                 // grad rho
-    R gry = c.drho1 * g1y + c.drho2 * g2y;
-    R fsx = mu1 * g1x + mu2 * g2x + mu3 * g3x;             // F_s
-    R fsy = mu1 * g1y + mu2 * g2y + mu3 * g3y;
-    R fx = fsx + rho * c.gx;
-    R fy = fsy + rho * c.gy;
+    const R g3x = -(g1x + g2x), g3y = -(g1y + g2y);        // c3 = 1 - c1 - c2
+    const R rho = c.rho3 + c.drho1 * c1 + c.drho2 * c2;    // Eq. 14
+    const R nu = c.nu3 + c.dnu1 * c1 + c.dnu2 * c2;        // Eq. 15
+    const R taug = R(3) * nu + R(0.5);                     // Eq. 18b
+    const R grx = c.drho1 * g1x + c.drho2 * g2x;           // grad rho
+    const R gry = c.drho1 * g1y + c.drho2 * g2y;
+    const R fsx = mu1 * g1x + mu2 * g2x + mu3 * g3x;       // F_s
+    const R fsy = mu1 * g1y + mu2 * g2y + mu3 * g3y;
+    const R fx = fsx + rho * c.gx;
+    const R fy = fsy + rho * c.gy;
     R mx = R(0), my = R(0), sum = R(0);
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
@@ -276,117 +235,528 @@ __device__ __forceinline__ NodeMacro<typename Tr<P>::R> node_macro(
         if (EY[k]) my += R(EY[k]) * gg[k];
         if (k) sum += gg[k];
     }
-    R irho = R(1) / rho;
-    R ux = (mx + R(0.5) * fx) * irho;
-    R uy = (my + R(0.5) * fy) * irho;
-    R a = c.am1 * lm1 + c.am2 * lm2;
-    R uu = ux * ux + uy * uy;
+    const R irho = R(1) / rho;
+    const R ux = (mx + R(0.5) * fx) * irho;
+    const R uy = (my + R(0.5) * fy) * irho;
+    const R a = c.am1 * lm1 + c.am2 * lm2;
+    const R uu = ux * ux + uy * uy;
     // c_s^2/(1-w0) = 3/5; s_0(u) = -w0 u.u/(2 c_s^2) = -(2/3) u.u
-    R p = R(0.6) * (sum + R(0.5) * (ux * grx + uy * gry) - rho * (R(2) / R(3)) * uu);
+    const R p = R(0.6) * (sum + R(0.5) * (ux * grx + uy * gry) - rho * (R(2) / R(3)) * uu);
     o.c1 = c1; o.c2 = c2; o.rho = rho; o.itg = R(1) / taug;
     o.mu1 = mu1; o.mu2 = mu2; o.ux = ux; o.uy = uy; o.p = p;
     o.grx = grx; o.gry = gry; o.fx = fx; o.fy = fy; o.fax = ux * a; o.fay = uy * a;
     return o;
 }
 
-// ------------------------------------------------------------------- step
 template <int P, int TY>
+__device__ __forceinline__ Stencil<typename Tr<P>::R> tile_stencil(const Smem<P, TY>& sm, int ci,
+                                                                   int mi) {
+    using SM = Smem<P, TY>;
+    Stencil<typename Tr<P>::R> s;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        s.c1[r] = &sm.c1[ci + (r - 1) * SM::CW];
+        s.c2[r] = &sm.c2[ci + (r - 1) * SM::CW];
+        s.m[r] = &sm.m[ci + (r - 1) * SM::CW];
+        s.mu1[r] = &sm.mu1[mi + (r - 1) * SM::MW];
+        s.mu2[r] = &sm.mu2[mi + (r - 1) * SM::MW];
+    }
+    s.mu3 = sm.mu3[mi];
+    return s;
+}
+
+// Chemical potentials of Eq. 8 at one fluid node from the c values of its
+// 3x3 neighbourhood (row pointers as in Stencil), with the wetting ghosts of
+// Eq. 42 across links into solid nodes.
+template <typename R>
+__device__ __forceinline__ void chem_pot(const R* const* c1r, const R* const* c2r,
+                                         const uint8_t* const* mr, const R* mt,
+                                         const Consts<R>& c, R& mu1, R& mu2, R& mu3) {
+    const R c1 = c1r[1][0], c2 = c2r[1][0];
+    const R c3 = R(1) - c1 - c2;
+    R l1 = R(0), l2 = R(0), l3 = R(0);
+#pragma unroll
+    for (int k = 1; k < 9; ++k) {
+        const int r = EY[k] + 1;
+        const int mn = mr[r][EX[k]];
+        R n1, n2, n3;
+        if (mn) {
+            const R* t = &mt[kMatStride * mn];
+            const R h1 = t[1] * c1 * c3 + t[0] * c1 * c2;
+            const R h2 = -t[0] * c1 * c2 + t[2] * c2 * c3;
+            const R h3 = -t[2] * c2 * c3 - t[1] * c1 * c3;
+            n1 = c1 + c.k4D * h1;
+            n2 = c2 + c.k4D * h2;
+            n3 = c3 + c.k4D * h3;
+        } else {
+            n1 = c1r[r][EX[k]];
+            n2 = c2r[r][EX[k]];
+            n3 = R(1) - n1 - n2;
+        }
+        l1 += wgt<R>(k) * (n1 - c1);
+        l2 += wgt<R>(k) * (n2 - c2);
+        l3 += wgt<R>(k) * (n3 - c3);
+    }
+    l1 *= R(6);  // 2 / c_s^2
+    l2 *= R(6);
+    l3 *= R(6);
+    const R tri = R(2) * c.lamT * c1 * c2 * (R(1) - c1 - c2);
+    mu1 = c.k12D * (c.lam1 * c1 * (R(1) - c1) * (R(1) - R(2) * c1) - tri) - c.k34D * c.lam1 * l1;
+    mu2 = c.k12D * (c.lam2 * c2 * (R(1) - c2) * (R(1) - R(2) * c2) - tri) - c.k34D * c.lam2 * l2;
+    mu3 = c.k12D * (c.lam3 * c3 * (R(1) - c3) * (R(1) - R(2) * c3) - tri) - c.k34D * c.lam3 * l3;
+}
+
+// Phase B of the tile kernels: chemical potentials on the mu region.
+template <int P, int TY>
+__device__ __forceinline__ void phase_b(Smem<P, TY>& sm, const Consts<typename Tr<P>::R>& c) {
+    using R = typename Tr<P>::R;
+    using SM = Smem<P, TY>;
+    for (int i = threadIdx.x; i < SM::MH * SM::MW; i += kThreads) {
+        const int my = i / SM::MW;
+        const int mx = i - my * SM::MW;
+        const int ci = (my + 1) * SM::CW + mx + 1;
+        R mu1 = R(0), mu2 = R(0), mu3 = R(0);
+        if (sm.m[ci] == 0) {
+            const R* c1r[3] = {&sm.c1[ci - SM::CW], &sm.c1[ci], &sm.c1[ci + SM::CW]};
+            const R* c2r[3] = {&sm.c2[ci - SM::CW], &sm.c2[ci], &sm.c2[ci + SM::CW]};
+            const uint8_t* mr[3] = {&sm.m[ci - SM::CW], &sm.m[ci], &sm.m[ci + SM::CW]};
+            chem_pot<R>(c1r, c2r, mr, sm.mt, c, mu1, mu2, mu3);
+        }
+        sm.mu1[i] = mu1;
+        sm.mu2[i] = mu2;
+        sm.mu3[i] = mu3;
+    }
+}
+
+// ------------------------------------------------------------------- step
+// The step kernel marches a workgroup (four wave64s) up a strip of 64
+// columns and H rows, four rows per iteration.  Lane l of every wave owns
+// column x0 - 2 + l; the 60 inner lanes produce output and the two lanes on
+// each side supply the 2-column halo of c (and 1-column halo of mu), so
+// every lane pulls exactly one node per row and neighbouring strips overlap
+// by four columns.  c (rows y-2..y+5) and mu (rows y-1..y+4) live in 16-row
+// LDS rings, so every population is pulled once per strip apart from the
+// overlap columns and 4 rows per strip.
+//   phase A: wave w forms c1, c2 of row Y+2+w from its prefetched pulls,
+//            issues the g / history loads of its phase-C row and then the
+//            pulls of row Y+6+w (next iteration); both complete while the
+//            workgroup runs phase B.
+//   phase B: mu on rows Y+1..Y+4, and each node's solid-neighbour mask.
+//   phase C: wave w updates row Y + ((w+2) & 3): waves 0, 1 the row they
+//            pulled in this iteration (still in registers), waves 2, 3 the
+//            row they pulled in the previous one (parked in a per-wave,
+//            double-buffered LDS stash).
+// Memory is addressed through buffer resources: one 32-bit lane offset per
+// lattice direction serves all 27 planes, the plane offset rides in an SGPR.
+// Every lane executes the same loads and the 31 main stores; a lane without
+// a fluid output node stores at an offset beyond the buffer's record count,
+// which the hardware discards, so no lane needs a branch around the stores
+// and the wait counts never cover the previous row's stores.  (The host
+// keeps every family buffer below 2 GiB, so that offset plus any plane
+// offset stays outside the record count.)
+constexpr int kOut = kTileX - 4;  // output columns per strip
+constexpr unsigned kDiscard = 0x80000000u;  // byte offset of a discarded store
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, gfx9 family
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void* p, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, int(bytes), kRsrcWord3);
+}
+
+template <int P>
+struct LatView {
+    rsrc_t fam[3];      // f^1, f^2, g: plane k of a family at byte offset k * pstride
+    rsrc_t rest;        // P16: FP32 rest planes f^1_0 (offset 0), f^2_0 (offset rstride)
+    unsigned pstride;   // bytes per plane
+    unsigned rstride;   // P16 rest-plane bytes
+};
+
+template <int P>
+__device__ __forceinline__ LatView<P> lat_view(const PopBuf& b, long npad) {
+    using S = typename Tr<P>::S;
+    LatView<P> v;
+    const unsigned ps = unsigned(npad * long(sizeof(S)));
+    const char* base = static_cast<const char*>(b.planes);
+#pragma unroll
+    for (int f = 0; f < 3; ++f) v.fam[f] = make_rsrc(base + long(f) * 9 * ps, 9u * ps);
+    v.pstride = ps;
+    v.rstride = unsigned(npad * 4);
+    v.rest = make_rsrc(P == P16 ? static_cast<const void*>(b.rest) : static_cast<const void*>(base),
+                       P == P16 ? 2u * v.rstride : ps);
+    return v;
+}
+
+// population k of family f at lattice node j (element offset within a plane)
+template <int P>
+__device__ __forceinline__ typename Tr<P>::R bld(const LatView<P>& v,
+                                                 const Consts<typename Tr<P>::R>& c, int f,
+                                                 int k, unsigned j) {
+    if constexpr (P == P64) {
+        auto r = __builtin_amdgcn_raw_buffer_load_b64(v.fam[f], int(j * 8u), int(k * v.pstride), 0);
+        return __builtin_bit_cast(double, r);
+    } else if constexpr (P == P32) {
+        unsigned r = __builtin_amdgcn_raw_buffer_load_b32(v.fam[f], int(j * 4u), int(k * v.pstride), 0);
+        return __builtin_bit_cast(float, r);
+    } else {
+        if (k == 0 && f < 2) {
+            unsigned r = __builtin_amdgcn_raw_buffer_load_b32(v.rest, int(j * 4u), int(f * v.rstride), 0);
+            return __builtin_bit_cast(float, r);
+        }
+        unsigned short r =
+            __builtin_amdgcn_raw_buffer_load_b16(v.fam[f], int(j * 2u), int(k * v.pstride), 0);
+        return float(__builtin_bit_cast(_Float16, r)) * c.iscale[f];
+    }
+}
+
+// store population k of family f at byte offset `ob` within its plane
+// (`orb` for the FP32 rest planes of P16)
+template <int P>
+__device__ __forceinline__ void bst(const LatView<P>& v, const Consts<typename Tr<P>::R>& c,
+                                    int f, int k, unsigned ob, unsigned orb,
+                                    typename Tr<P>::R x) {
+    if constexpr (P == P64) {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(decltype(
+            __builtin_amdgcn_raw_buffer_load_b64(v.fam[f], 0, 0, 0)), x), v.fam[f], int(ob),
+            int(k * v.pstride), 0);
+    } else if constexpr (P == P32) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), v.fam[f], int(ob),
+                                              int(k * v.pstride), 0);
+    } else {
+        if (k == 0 && f < 2) {
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), v.rest,
+                                                  int(orb), int(f * v.rstride), 0);
+            return;
+        }
+        const _Float16 h = _Float16(x * c.scale[f]);
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h), v.fam[f],
+                                              int(ob), int(k * v.pstride), 0);
+    }
+}
+
+template <int P>
+struct Ring {
+    using R = typename Tr<P>::R;
+    static constexpr int W = kTileX;  // ring columns = lanes
+    static constexpr int NR = 16;     // ring rows
+    R c1[NR * W];
+    R c2[NR * W];
+    R mu1[NR * W];
+    R mu2[NR * W];
+    R mu3[NR * W];
+    R stash[2][2][18][W];             // [buffer][wave-2][population][lane]
+    R mt[kMatStride * (kMaxMaterials + 1)];
+    uint16_t nmask[NR * W];           // bit k-1: neighbour e_k solid; bit 8: node solid
+    uint8_t m[NR * W];
+};
+
+__device__ __forceinline__ int ring_slot(int y, int y0) { return (y - y0 + 4) & 15; }
+
+// wrapped neighbourhood of (x, y) as 32-bit element offsets
+struct Nb32 {
+    unsigned xm, x0, xp, rm, r0, rp;
+    __device__ __forceinline__ unsigned at(int dx, int dy) const {
+        const unsigned r = dy < 0 ? rm : (dy > 0 ? rp : r0);
+        const unsigned x = dx < 0 ? xm : (dx > 0 ? xp : x0);
+        return r + x;
+    }
+    __device__ __forceinline__ unsigned up(int k) const { return at(-EX[k], -EY[k]); }
+    __device__ __forceinline__ unsigned dn(int k) const { return at(EX[k], EY[k]); }
+};
+
+__device__ __forceinline__ Nb32 make_nb32(const Grid& g, int x, int y) {
+    Nb32 n;
+    n.x0 = unsigned(x);
+    n.xm = unsigned(x == 0 ? g.nx - 1 : x - 1);
+    n.xp = unsigned(x == g.nx - 1 ? 0 : x + 1);
+    n.r0 = unsigned(y) * unsigned(g.pitch);
+    n.rm = unsigned(y == 0 ? g.ny - 1 : y - 1) * unsigned(g.pitch);
+    n.rp = unsigned(y == g.ny - 1 ? 0 : y + 1) * unsigned(g.pitch);
+    return n;
+}
+
+// Issues the material byte and the 18 pulls of f^1, f^2 at node (gx, gy).
+// The pulls are issued whatever the material (every wrapped offset is
+// valid), so nothing waits on the byte before they go out; the values of a
+// solid node are discarded where c is formed.
+template <int P>
+__device__ __forceinline__ void pull_f(const Grid& g, const Consts<typename Tr<P>::R>& c,
+                                       const LatView<P>& src, const uint8_t* __restrict__ mat,
+                                       int gx, int gy, typename Tr<P>::R* f1,
+                                       typename Tr<P>::R* f2, uint8_t& m) {
+    const Nb32 nb = make_nb32(g, gx, gy);
+    m = mat[nb.r0 + nb.x0];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const unsigned j = nb.up(k);
+        f1[k] = bld<P>(src, c, 0, k, j);
+        f2[k] = bld<P>(src, c, 1, k, j);
+    }
+}
+
+// Chemical potentials of one mu-ring node and its solid-neighbour mask.
+template <int P>
+__device__ __forceinline__ void ring_mu(Ring<P>& sm, const Consts<typename Tr<P>::R>& c,
+                                        int y, int y0, int col) {
+    using R = typename Tr<P>::R;
+    using RG = Ring<P>;
+    const int sc[3] = {ring_slot(y - 1, y0), ring_slot(y, y0), ring_slot(y + 1, y0)};
+    const R* c1r[3];
+    const R* c2r[3];
+    const uint8_t* mr[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        c1r[q] = &sm.c1[sc[q] * RG::W + col];
+        c2r[q] = &sm.c2[sc[q] * RG::W + col];
+        mr[q] = &sm.m[sc[q] * RG::W + col];
+    }
+    unsigned mask = mr[1][0] ? 256u : 0u;
+#pragma unroll
+    for (int k = 1; k < 9; ++k)
+        if (mr[EY[k] + 1][EX[k]]) mask |= 1u << (k - 1);
+    R mu1 = R(0), mu2 = R(0), mu3 = R(0);
+    if (!(mask & 256u)) {
+        if (mask == 0) {
+            // bulk node: plain Laplacian (Eq. 20b)
+            const R a1 = c1r[1][0], a2 = c2r[1][0], a3 = R(1) - a1 - a2;
+            R l1 = R(0), l2 = R(0), l3 = R(0);
+#pragma unroll
+            for (int k = 1; k < 9; ++k) {
+                const R n1 = c1r[EY[k] + 1][EX[k]], n2 = c2r[EY[k] + 1][EX[k]];
+                l1 += wgt<R>(k) * (n1 - a1);
+                l2 += wgt<R>(k) * (n2 - a2);
+                l3 += wgt<R>(k) * ((R(1) - n1 - n2) - a3);
+            }
+            l1 *= R(6);
+            l2 *= R(6);
+            l3 *= R(6);
+            const R tri = R(2) * c.lamT * a1 * a2 * (R(1) - a1 - a2);
+            mu1 = c.k12D * (c.lam1 * a1 * (R(1) - a1) * (R(1) - R(2) * a1) - tri) - c.k34D * c.lam1 * l1;
+            mu2 = c.k12D * (c.lam2 * a2 * (R(1) - a2) * (R(1) - R(2) * a2) - tri) - c.k34D * c.lam2 * l2;
+            mu3 = c.k12D * (c.lam3 * a3 * (R(1) - a3) * (R(1) - R(2) * a3) - tri) - c.k34D * c.lam3 * l3;
+        } else {
+            chem_pot<R>(c1r, c2r, mr, sm.mt, c, mu1, mu2, mu3);
+        }
+    }
+    const int o = sc[1] * RG::W + col;
+    sm.mu1[o] = mu1;
+    sm.mu2[o] = mu2;
+    sm.mu3[o] = mu3;
+    sm.nmask[o] = uint16_t(mask);
+}
+
+// Phase C of one node: time derivative (Eq. 19 in Eq. 11a), history,
+// equilibria (Eqs. 2, 4), sources (Eq. 11), BGK collision (Eq. 45), the 27
+// population stores at the node (or the spare row when `live` is false) and,
+// for a node next to solids, half-way bounce-back into the solid slots
+// (Eq. 44) with the moving-wall term -2 w_k a e_k.u_w / c_s^2 (a = c_i for
+// f^i, rho for g).
+template <int P>
+__device__ __forceinline__ void node_update(const Grid& g, const Consts<typename Tr<P>::R>& c,
+                                            const Stencil<typename Tr<P>::R>& s,
+                                            const typename Tr<P>::R* mt, const Nb32& nb,
+                                            unsigned idx, bool live, unsigned mask,
+                                            typename Tr<P>::R* f1, typename Tr<P>::R* f2,
+                                            const typename Tr<P>::R* gg,
+                                            const typename Tr<P>::R* ho, const LatView<P>& dst,
+                                            rsrc_t hist, unsigned hstride) {
+    using R = typename Tr<P>::R;
+    using HT = typename Tr<P>::H;
+    const NodeMacro<R> o = node_macro<R, true>(s, c, gg, mask);
+    const R d1x = o.c1 * o.ux - ho[0] * ho[2], d1y = o.c1 * o.uy - ho[0] * ho[3];
+    const R d2x = o.c2 * o.ux - ho[1] * ho[2], d2y = o.c2 * o.uy - ho[1] * ho[3];
+    // byte offsets of this node's slots, or kDiscard for a lane without a
+    // fluid output node
+    const unsigned ob = live ? idx * unsigned(sizeof(typename Tr<P>::S)) : kDiscard;
+    const unsigned o4 = live ? idx * 4u : kDiscard;
+    {
+        const HT hv[4] = {HT(o.c1), HT(o.c2), HT(o.ux), HT(o.uy)};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if constexpr (P == P64)
+                __builtin_amdgcn_raw_buffer_store_b64(
+                    __builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(hist, 0, 0, 0)),
+                                       hv[q]),
+                    hist, int(ob), int(q * hstride), 0);
+            else
+                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, hv[q]), hist,
+                                                      int(o4), int(q * hstride), 0);
+        }
+    }
+    const R uu = o.ux * o.ux + o.uy * o.uy;
+    const R em1 = c.eta1 * o.mu1, em2 = c.eta2 * o.mu2;
+    const R p3 = R(3) * o.p;
+    const R fsg = R(1) - R(0.5) * o.itg;
+    R g2[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const R w = wgt<R>(k);
+        const R eu = R(EX[k]) * o.ux + R(EY[k]) * o.uy;
+        R fe1, fe2, ge;
+        const R sk = w * (R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu);  // Eq. 4
+        if (k == 0) {                                                    // Eqs. 2a, 2b
+            fe1 = o.c1 + (w - R(1)) * em1;
+            fe2 = o.c2 + (w - R(1)) * em2;
+            ge = p3 * (w - R(1)) + o.rho * sk;
+        } else {
+            fe1 = w * (em1 + R(3) * o.c1 * eu);
+            fe2 = w * (em2 + R(3) * o.c2 * eu);
+            ge = p3 * w + o.rho * sk;
+        }
+        const R ed1 = R(EX[k]) * d1x + R(EY[k]) * d1y;                   // Eq. 11a
+        const R ed2 = R(EX[k]) * d2x + R(EY[k]) * d2y;
+        const R bx = sk * o.grx + (sk + w) * R(3) * o.fx;                // Eq. 11b
+        const R by = sk * o.gry + (sk + w) * R(3) * o.fy;
+        const R gk = fsg * ((R(EX[k]) - o.ux) * bx + (R(EY[k]) - o.uy) * by)
+                   + R(3) * w * (R(EX[k]) * o.fax + R(EY[k]) * o.fay);
+        f1[k] = f1[k] + (fe1 - f1[k]) * c.itau1 + c.fs1 * R(3) * w * ed1;  // Eq. 45
+        f2[k] = f2[k] + (fe2 - f2[k]) * c.itau2 + c.fs2 * R(3) * w * ed2;
+        g2[k] = gg[k] + (ge - gg[k]) * o.itg + gk;
+        bst<P>(dst, c, 0, k, ob, o4, f1[k]);
+        bst<P>(dst, c, 1, k, ob, o4, f2[k]);
+        bst<P>(dst, c, 2, k, ob, o4, g2[k]);
+    }
+    if (live && (mask & 255u)) {
+#pragma unroll
+        for (int k = 1; k < 9; ++k) {
+            if (mask & (1u << (k - 1))) {
+                const int mn = s.m[EY[k] + 1][EX[k]];
+                const R* tm = &mt[kMatStride * mn];
+                const R corr = -R(6) * wgt<R>(k) * (R(EX[k]) * tm[3] + R(EY[k]) * tm[4]);
+                const unsigned sn = nb.dn(k);
+                const unsigned sb = sn * unsigned(sizeof(typename Tr<P>::S)), s4 = sn * 4u;
+                bst<P>(dst, c, 0, OPP[k], sb, s4, f1[k] + corr * o.c1);
+                bst<P>(dst, c, 1, OPP[k], sb, s4, f2[k] + corr * o.c2);
+                bst<P>(dst, c, 2, OPP[k], sb, s4, g2[k] + corr * o.rho);
+            }
+        }
+    }
+}
+
+template <int P, int H>
 __global__ __launch_bounds__(kThreads) void step_kernel(Grid g, Consts<typename Tr<P>::R> c,
                                                         const uint8_t* __restrict__ mat,
                                                         const double* __restrict__ mtab,
-                                                        PopBuf src, PopBuf dst,
-                                                        typename Tr<P>::H* __restrict__ hist) {
+                                                        PopBuf srcb, PopBuf dstb,
+                                                        typename Tr<P>::H* __restrict__ histp) {
     using R = typename Tr<P>::R;
-    using SM = Smem<P, TY>;
-    __shared__ SM sm;
+    using HT = typename Tr<P>::H;
+    using RG = Ring<P>;
+    __shared__ RG sm;
     const int t = tile_of(blockIdx.x, g.tiles_x * g.tiles_y);
-    const int x0 = (t % g.tiles_x) * kTileX;
-    const int y0 = (t / g.tiles_x) * TY;
-    load_mtab<P, TY>(sm, mtab);
-    phase_a<P, TY, true>(sm, g, c, mat, src, nullptr, x0, y0);
-    __syncthreads();
-    phase_b<P, TY>(sm, c);
-    __syncthreads();
+    const int x0 = (t % g.tiles_x) * kOut;
+    const int y0 = (t / g.tiles_x) * H;
+    const int rows = g.ny - y0 < H ? g.ny - y0 : H;
+    const int nit = (rows + 3) / 4;
+    const int lane = threadIdx.x & (kTileX - 1);
+    const int w = threadIdx.x / kTileX;
+    const int gxl = wrapc(x0 - 2 + lane, g.nx);            // this lane's column
+    const bool out_lane = lane >= 2 && lane < kTileX - 2 && x0 + lane - 2 < g.nx;
+    const LatView<P> src = lat_view<P>(srcb, g.npad);
+    const LatView<P> dst = lat_view<P>(dstb, g.npad);
+    const unsigned hstride = unsigned(g.npad * long(sizeof(HT)));
+    const rsrc_t hist = make_rsrc(histp, 4u * hstride);
+    for (int i = threadIdx.x; i < kMatStride * (kMaxMaterials + 1); i += kThreads)
+        sm.mt[i] = R(mtab[i]);
 
-    const int tx = threadIdx.x & (kTileX - 1);
-    const int gx = x0 + tx;
-    if (gx >= g.nx) return;
-    for (int ty = threadIdx.x / kTileX; ty < TY; ty += kThreads / kTileX) {
-        const int gy = y0 + ty;
-        if (gy >= g.ny) break;
-        const int ci = (ty + 2) * SM::CW + tx + 2;
-        const int mi = (ty + 1) * SM::MW + tx + 1;
-        if (sm.m[ci]) continue;
-        const Nb nb = make_nb(g, gx, gy);
-        const long idx = nb.r0 + gx;
-        R f1[9], f2[9], gg[9];
+    R nf1[9], nf2[9], cf1[9], cf2[9], gg[9], ho[4];
+    uint8_t nm;
+    Nb32 nb;
+    unsigned idx = 0;
+    int yo = 0;
+
+    // phase A of iteration it: c of row Y+2+w from the prefetched pulls, then
+    // the phase-C operands of iteration it, then the pulls for iteration it+1
+    auto phase_a = [&](int it) {
+        const int Y = y0 + 4 * it;
+        const int sl = ring_slot(Y + 2 + w, y0) * RG::W + lane;
+        R a = R(0), b = R(0);
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            long j = nb.up(k);
-            f1[k] = ld<P>(src, c, k, g.npad, j);
-            f2[k] = ld<P>(src, c, 9 + k, g.npad, j);
-            gg[k] = ld<P>(src, c, 18 + k, g.npad, j);
+            cf1[k] = nf1[k];
+            cf2[k] = nf2[k];
+            a += cf1[k];
+            b += cf2[k];
         }
-        const R c1o = R(hist[idx]), c2o = R(hist[g.npad + idx]);
-        const R uxo = R(hist[2 * g.npad + idx]), uyo = R(hist[3 * g.npad + idx]);
-        NodeMacro<R> o = node_macro<P, TY>(sm, c, ci, mi, gg);
-        // Euler time derivative of c_i u (Eq. 19 inside Eq. 11a)
-        const R d1x = o.c1 * o.ux - c1o * uxo, d1y = o.c1 * o.uy - c1o * uyo;
-        const R d2x = o.c2 * o.ux - c2o * uxo, d2y = o.c2 * o.uy - c2o * uyo;
-        hist[idx] = typename Tr<P>::H(o.c1);
-        hist[g.npad + idx] = typename Tr<P>::H(o.c2);
-        hist[2 * g.npad + idx] = typename Tr<P>::H(o.ux);
-        hist[3 * g.npad + idx] = typename Tr<P>::H(o.uy);
+        const bool fl = nm == 0;
+        sm.c1[sl] = fl ? a : R(0);
+        sm.c2[sl] = fl ? b : R(0);
+        sm.m[sl] = nm;
+        if (w >= 2) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                sm.stash[it & 1][w - 2][k][lane] = cf1[k];
+                sm.stash[it & 1][w - 2][9 + k][lane] = cf2[k];
+            }
+        }
+        // issued on every path, at in-range offsets, before the next row's
+        // pulls so that waiting for them leaves those in flight
+        yo = Y + ((w + 2) & 3);
+        nb = make_nb32(g, gxl, wrapc(yo, g.ny));
+        idx = nb.r0 + nb.x0;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) gg[k] = bld<P>(src, c, 2, k, nb.up(k));
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if constexpr (P == P64)
+                ho[q] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+                                                       hist, int(idx * 8u), int(q * hstride), 0));
+            else
+                ho[q] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                                      hist, int(idx * 4u), int(q * hstride), 0));
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        pull_f<P>(g, c, src, mat, gxl, wrapc(Y + 6 + w, g.ny), nf1, nf2, nm);
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    // phase B of iteration it: mu on rows Y+1..Y+4, ring columns 1..62
+    auto phase_b = [&](int it) {
+        const int Y = y0 + 4 * it;
+        if (threadIdx.x < 4 * (kTileX - 2)) {
+            const int r = threadIdx.x / (kTileX - 2);
+            const int col = threadIdx.x - r * (kTileX - 2) + 1;
+            const int y = Y + 1 + r;
+            if (y >= y0 - 1) ring_mu<P>(sm, c, y, y0, col);  // prologue: rows below y0-1 lack neighbours
+        }
+    };
 
-        const R uu = o.ux * o.ux + o.uy * o.uy;
-        const R em1 = c.eta1 * o.mu1, em2 = c.eta2 * o.mu2;
-        const R p3 = R(3) * o.p;
-        const R fsg = R(1) - R(0.5) * o.itg;
+    pull_f<P>(g, c, src, mat, gxl, wrapc(y0 - 2 + w, g.ny), nf1, nf2, nm);
+    phase_a(-1);
+    __syncthreads();
+    phase_b(-1);
+    __syncthreads();
+    phase_a(0);
+    for (int it = 0; it < nit; ++it) {
+        __syncthreads();
+        phase_b(it);
+        __syncthreads();
+        // ---- phase C
+        {
+            Stencil<R> s;
+            const int sl[3] = {ring_slot(yo - 1, y0), ring_slot(yo, y0), ring_slot(yo + 1, y0)};
 #pragma unroll
-        for (int k = 0; k < 9; ++k) {
-            const R w = wgt<R>(k);
-            const R eu = R(EX[k]) * o.ux + R(EY[k]) * o.uy;
-            // Eq. 2a
-            R fe1, fe2, ge;
-            const R sk = w * (R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu);  // Eq. 4
-            if (k == 0) {
-                fe1 = o.c1 + (w - R(1)) * em1;
-                fe2 = o.c2 + (w - R(1)) * em2;
-                ge = p3 * (w - R(1)) + o.rho * sk;                           // Eq. 2b
-            } else {
-                fe1 = w * (em1 + R(3) * o.c1 * eu);
-                fe2 = w * (em2 + R(3) * o.c2 * eu);
-                ge = p3 * w + o.rho * sk;
+            for (int r = 0; r < 3; ++r) {
+                s.c1[r] = &sm.c1[sl[r] * RG::W + lane];
+                s.c2[r] = &sm.c2[sl[r] * RG::W + lane];
+                s.m[r] = &sm.m[sl[r] * RG::W + lane];
+                s.mu1[r] = &sm.mu1[sl[r] * RG::W + lane];
+                s.mu2[r] = &sm.mu2[sl[r] * RG::W + lane];
             }
-            // Eq. 11a, Eq. 11b
-            const R ed1 = R(EX[k]) * d1x + R(EY[k]) * d1y;
-            const R ed2 = R(EX[k]) * d2x + R(EY[k]) * d2y;
-            const R bx = sk * o.grx + (sk + w) * R(3) * o.fx;
-            const R by = sk * o.gry + (sk + w) * R(3) * o.fy;
-            const R gk = fsg * ((R(EX[k]) - o.ux) * bx + (R(EY[k]) - o.uy) * by)
-                       + R(3) * w * (R(EX[k]) * o.fax + R(EY[k]) * o.fay);
-            // BGK collision (Eq. 45)
-            f1[k] = f1[k] + (fe1 - f1[k]) * c.itau1 + c.fs1 * R(3) * w * ed1;
-            f2[k] = f2[k] + (fe2 - f2[k]) * c.itau2 + c.fs2 * R(3) * w * ed2;
-            gg[k] = gg[k] + (ge - gg[k]) * o.itg + gk;
-            st<P>(dst, c, k, g.npad, idx, f1[k]);
-            st<P>(dst, c, 9 + k, g.npad, idx, f2[k]);
-            st<P>(dst, c, 18 + k, g.npad, idx, gg[k]);
-        }
-        // half-way bounce-back into solid neighbours (Eq. 44), with the
-        // moving-wall term -2 w_k a e_k.u_w / c_s^2 (a = c_i for f^i, rho for g)
+            s.mu3 = sm.mu3[sl[1] * RG::W + lane];
+            const unsigned mask = out_lane ? unsigned(sm.nmask[sl[1] * RG::W + lane]) : 256u;
+            const bool live = out_lane && yo < y0 + rows && !(mask & 256u);
+            if (w >= 2) {
 #pragma unroll
-        for (int k = 1; k < 9; ++k) {
-            const int mn = sm.m[ci + EY[k] * SM::CW + EX[k]];
-            if (mn) {
-                const R* tm = &sm.mt[kMatStride * mn];
-                const R corr = -R(6) * wgt<R>(k) * (R(EX[k]) * tm[3] + R(EY[k]) * tm[4]);
-                const long s = nb.dn(k);
-                st<P>(dst, c, OPP[k], g.npad, s, f1[k] + corr * o.c1);
-                st<P>(dst, c, 9 + OPP[k], g.npad, s, f2[k] + corr * o.c2);
-                st<P>(dst, c, 18 + OPP[k], g.npad, s, gg[k] + corr * o.rho);
+                for (int k = 0; k < 9; ++k) {
+                    cf1[k] = sm.stash[(it - 1) & 1][w - 2][k][lane];
+                    cf2[k] = sm.stash[(it - 1) & 1][w - 2][9 + k][lane];
+                }
             }
+            node_update<P>(g, c, s, sm.mt, nb, idx, live, mask, cf1, cf2, gg, ho, dst,
+                           hist, hstride);
         }
+        // phase A of the next iteration (after the last one it only issues
+        // harmless in-range loads)
+        phase_a(it + 1);
     }
 }
 
@@ -404,8 +774,9 @@ __global__ __launch_bounds__(kThreads) void init_kernel(Grid g, Consts<typename 
     using SM = Smem<P, TY>;
     __shared__ SM sm;
     const int t = blockIdx.x;
-    const int x0 = (t % g.tiles_x) * kTileX;
-    const int y0 = (t / g.tiles_x) * TY;
+    const int ntx = (g.nx + kTileX - 1) / kTileX;
+    const int x0 = (t % ntx) * kTileX;
+    const int y0 = (t / ntx) * TY;
     load_mtab<P, TY>(sm, mtab);
     phase_a<P, TY, false>(sm, g, c, mat, PopBuf{nullptr, nullptr}, in4, x0, y0);
     __syncthreads();
@@ -469,8 +840,9 @@ __global__ __launch_bounds__(kThreads) void readout_kernel(Grid g, Consts<typena
     using SM = Smem<P, TY>;
     __shared__ SM sm;
     const int t = blockIdx.x;
-    const int x0 = (t % g.tiles_x) * kTileX;
-    const int y0 = (t / g.tiles_x) * TY;
+    const int ntx = (g.nx + kTileX - 1) / kTileX;
+    const int x0 = (t % ntx) * kTileX;
+    const int y0 = (t / ntx) * TY;
     load_mtab<P, TY>(sm, mtab);
     phase_a<P, TY, true>(sm, g, c, mat, src, nullptr, x0, y0);
     __syncthreads();
@@ -494,7 +866,7 @@ __global__ __launch_bounds__(kThreads) void readout_kernel(Grid g, Consts<typena
         R gg[9];
 #pragma unroll
         for (int k = 0; k < 9; ++k) gg[k] = ld<P>(src, c, 18 + k, g.npad, nb.up(k));
-        NodeMacro<R> o = node_macro<P, TY>(sm, c, ci, mi, gg);
+        NodeMacro<R> o = node_macro<R>(tile_stencil<P, TY>(sm, ci, mi), c, gg);
         out[0 * n + hi] = double(o.c1);
         out[1 * n + hi] = double(o.c2);
         out[2 * n + hi] = double(R(1) - o.c1 - o.c2);
@@ -601,10 +973,10 @@ template <int P>
 hipError_t step_p(const Grid& g, const void* consts, const uint8_t* mat, const double* mtab,
                   PopBuf src, PopBuf dst, void* hist, hipStream_t s) {
     switch (g.tile_rows) {
-        case 2: return step_ty<P, 2>(g, consts, mat, mtab, src, dst, hist, s);
-        case 4: return step_ty<P, 4>(g, consts, mat, mtab, src, dst, hist, s);
-        case 8: return step_ty<P, 8>(g, consts, mat, mtab, src, dst, hist, s);
         case 16: return step_ty<P, 16>(g, consts, mat, mtab, src, dst, hist, s);
+        case 32: return step_ty<P, 32>(g, consts, mat, mtab, src, dst, hist, s);
+        case 64: return step_ty<P, 64>(g, consts, mat, mtab, src, dst, hist, s);
+        case 128: return step_ty<P, 128>(g, consts, mat, mtab, src, dst, hist, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -628,7 +1000,7 @@ template <int P>
 static hipError_t init_p(const Grid& g, const void* consts, const uint8_t* mat,
                          const double* mtab, const double* in4, PopBuf dst, void* hist,
                          hipStream_t s) {
-    int nt = g.tiles_x * ((g.ny + kAuxRows - 1) / kAuxRows);
+    int nt = ((g.nx + kTileX - 1) / kTileX) * ((g.ny + kAuxRows - 1) / kAuxRows);
     hipLaunchKernelGGL((init_kernel<P, kAuxRows>), dim3(nt), dim3(kThreads), 0, s, g,
                        *static_cast<const CT<P>*>(consts), mat, mtab, in4, dst,
                        static_cast<typename Tr<P>::H*>(hist));
@@ -649,7 +1021,7 @@ hipError_t launch_init(int prec, const Grid& g, const void* consts, const uint8_
 template <int P>
 static hipError_t readout_p(const Grid& g, const void* consts, const uint8_t* mat,
                             const double* mtab, PopBuf src, double* out, hipStream_t s) {
-    int nt = g.tiles_x * ((g.ny + kAuxRows - 1) / kAuxRows);
+    int nt = ((g.nx + kTileX - 1) / kTileX) * ((g.ny + kAuxRows - 1) / kAuxRows);
     hipLaunchKernelGGL((readout_kernel<P, kAuxRows>), dim3(nt), dim3(kThreads), 0, s, g,
                        *static_cast<const CT<P>*>(consts), mat, mtab, src, out);
     return hipGetLastError();

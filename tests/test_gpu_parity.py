@@ -92,11 +92,11 @@ def test_random_three_phase(tlb, geometry, nx, ny, U):
     assert_parity(g, o)
 
 
-@pytest.mark.parametrize("rows", [2, 4, 16])
+@pytest.mark.parametrize("rows", [16, 32, 128])
 def test_tile_shape_invariance(tlb, rows):
-    """Results do not depend on the workgroup tile height (bitwise)."""
+    """Results do not depend on the strip height of the step kernel (bitwise)."""
     p = W.random_fields(130, 70, geometry="cylinder")
-    a, _ = run_pair(tlb, p, 50, rows=8)
+    a, _ = run_pair(tlb, p, 50, rows=64)
     b = tlb.from_problem(p)
     b.set_tile_rows(rows)
     b.step(50)
