@@ -159,7 +159,7 @@ tlb_status tlb_time_steps(tlb_ctx* ctx, int64_t nsteps, double* ms_per_step);
 
 /* Rows of the strip one workgroup of the step kernel marches through
  * (tuning knob; results are bitwise identical for every legal value).
- * rows in {16, 32, 64, 128}; default 16. */
+ * rows: a multiple of 4 in [8, 4096]; default 64. */
 tlb_status tlb_set_tile_rows(tlb_ctx* ctx, int rows);
 
 /* Last error message of ctx, or of the calling thread's last failed

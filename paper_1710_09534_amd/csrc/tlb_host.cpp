@@ -144,7 +144,7 @@ void set_grid(tlb_ctx* c, int rows) {
     c->grid.pitch = c->L.pitch;
     c->grid.npad = long(c->L.npad);
     c->grid.tile_rows = rows;
-    c->grid.tiles_x = (c->nx + kStripOut - 1) / kStripOut;   // step-kernel strips
+    c->grid.tiles_x = (c->nx + kTileX - 1) / kTileX;   // 64-column strips
     c->grid.tiles_y = (c->ny + rows - 1) / rows;
 }
 
@@ -226,7 +226,7 @@ tlb_status tlb_create(int nx, int ny, tlb_precision p, const tlb_fluid* fl, void
     c->eta[1] = c->M[1] / (cs2 * (fl->tau2 - 0.5));
     fill_consts(c->c64, c);
     fill_consts(c->c32, c);
-    set_grid(c, 16);
+    set_grid(c, 64);
     if (hipHostMalloc(reinterpret_cast<void**>(&c->health), 4 * sizeof(double)) != hipSuccess) {
         delete c;
         return fail(nullptr, TLB_ENOMEM, "pinned health word");
@@ -383,8 +383,8 @@ tlb_status tlb_set_check_interval(tlb_ctx* c, int64_t interval) {
 int64_t tlb_step_count(const tlb_ctx* c) { return c ? c->steps : -1; }
 
 tlb_status tlb_set_tile_rows(tlb_ctx* c, int rows) {
-    if (!c || (rows != 16 && rows != 32 && rows != 64 && rows != 128))
-        return fail(c, TLB_EINVAL, "strip rows must be 16, 32, 64 or 128");
+    if (!c || rows < 8 || rows > 4096 || rows % 4)
+        return fail(c, TLB_EINVAL, "strip rows must be a multiple of 4 in [8, 4096]");
     set_grid(c, rows);
     return TLB_OK;
 }

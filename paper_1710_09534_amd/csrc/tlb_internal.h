@@ -10,8 +10,7 @@ namespace tlb {
 
 constexpr int kMaxMaterials = 15;
 constexpr int kTileX = 64;        // interior columns per workgroup (one wave64 row)
-constexpr int kThreads = 256;     // four wave64s per workgroup
-constexpr int kStripOut = kTileX - 4;  // output columns of a step-kernel strip
+constexpr int kThreads = 256;     // four wave64s per workgroup (auxiliary kernels)
 constexpr int kReduceBlocks = 512;
 
 enum Precision : int { P64 = 0, P32 = 1, P16 = 2 };

@@ -197,10 +197,11 @@ __device__ __forceinline__ NodeMacro<R> node_macro(const Stencil<R>& s, const Co
     const R c1 = s.c1[1][0], c2 = s.c2[1][0];
     const R mu1 = s.mu1[1][0], mu2 = s.mu2[1][0], mu3 = s.mu3;
     R g1x = R(0), g1y = R(0), g2x = R(0), g2y = R(0), lm1 = R(0), lm2 = R(0);
+    const bool any = MASK ? (mask & 255u) != 0u : true;
 #pragma unroll
     for (int k = 1; k < 9; ++k) {
         const int r = EY[k] + 1;
-        const bool solid = MASK ? ((mask >> (k - 1)) & 1u) != 0u : s.m[r][EX[k]] != 0;
+        const bool solid = any && (MASK ? ((mask >> (k - 1)) & 1u) != 0u : s.m[r][EX[k]] != 0);
         const R v1 = solid ? c1 : s.c1[r][EX[k]];
         const R v2 = solid ? c2 : s.c2[r][EX[k]];
         const R w1 = solid ? mu1 : s.mu1[r][EX[k]];
@@ -329,32 +330,34 @@ __device__ __forceinline__ void phase_b(Smem<P, TY>& sm, const Consts<typename T
 }
 
 // ------------------------------------------------------------------- step
-// The step kernel marches a workgroup (four wave64s) up a strip of 64
-// columns and H rows, four rows per iteration.  Lane l of every wave owns
-// column x0 - 2 + l; the 60 inner lanes produce output and the two lanes on
-// each side supply the 2-column halo of c (and 1-column halo of mu), so
-// every lane pulls exactly one node per row and neighbouring strips overlap
-// by four columns.  c (rows y-2..y+5) and mu (rows y-1..y+4) live in 16-row
-// LDS rings, so every population is pulled once per strip apart from the
-// overlap columns and 4 rows per strip.
-//   phase A: wave w forms c1, c2 of row Y+2+w from its prefetched pulls,
-//            issues the g / history loads of its phase-C row and then the
-//            pulls of row Y+6+w (next iteration); both complete while the
-//            workgroup runs phase B.
+// The step kernel marches a workgroup up a strip of 64 columns and H rows,
+// four rows per iteration.  Waves 0..3 (the row waves) own the strip's 64
+// columns, one lane per column, so every row of every plane is read and
+// written as whole, aligned 64-node segments; wave 4 (the halo wave) forms c
+// on the two columns either side of the strip.  c (rows y-2..y+5) and mu
+// (rows y-1..y+4) live in LDS rings, so every population is pulled once per
+// strip apart from the side halo and 4 rows per strip.
+//   phase A: row wave w forms c1, c2 of row Y+2+w from its prefetched
+//            pulls, issues the g / history loads of its phase-C row and then
+//            the pulls of row Y+6+w (next iteration); the halo wave does the
+//            same for the 16 halo nodes of rows Y+2..Y+5.  The loads complete
+//            while the workgroup runs phase B.
 //   phase B: mu on rows Y+1..Y+4, and each node's solid-neighbour mask.
-//   phase C: wave w updates row Y + ((w+2) & 3): waves 0, 1 the row they
+//   phase C: row wave w updates row Y + ((w+2) & 3): waves 0, 1 the row they
 //            pulled in this iteration (still in registers), waves 2, 3 the
 //            row they pulled in the previous one (parked in a per-wave,
 //            double-buffered LDS stash).
+// The row waves and the halo wave run separate loops with the same barrier
+// sequence, so the compiler's wait counts for each follow its own stores.
 // Memory is addressed through buffer resources: one 32-bit lane offset per
 // lattice direction serves all 27 planes, the plane offset rides in an SGPR.
-// Every lane executes the same loads and the 31 main stores; a lane without
-// a fluid output node stores at an offset beyond the buffer's record count,
-// which the hardware discards, so no lane needs a branch around the stores
-// and the wait counts never cover the previous row's stores.  (The host
-// keeps every family buffer below 2 GiB, so that offset plus any plane
+// Every row-wave lane executes the same loads and the 31 main stores; a lane
+// without a fluid output node stores at an offset beyond the buffer's record
+// count, which the hardware discards, so no lane needs a branch around the
+// stores and the wait counts never cover the previous row's stores.  (The
+// host keeps every family buffer below 2 GiB, so that offset plus any plane
 // offset stays outside the record count.)
-constexpr int kOut = kTileX - 4;  // output columns per strip
+constexpr int kStepThreads = 5 * kTileX;  // four row waves and the halo wave
 constexpr unsigned kDiscard = 0x80000000u;  // byte offset of a discarded store
 using rsrc_t = __amdgpu_buffer_rsrc_t;
 constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, gfx9 family
@@ -436,20 +439,24 @@ __device__ __forceinline__ void bst(const LatView<P>& v, const Consts<typename T
 template <int P>
 struct Ring {
     using R = typename Tr<P>::R;
-    static constexpr int W = kTileX;  // ring columns = lanes
-    static constexpr int NR = 16;     // ring rows
+    static constexpr int W = kTileX + 4;   // c ring columns x0-2 .. x0+65
+    static constexpr int MW = kTileX + 2;  // mu ring columns x0-1 .. x0+64
+    static constexpr int NR = 16;          // c ring rows (rows Y-1..Y+9 live at once)
+    static constexpr int NM = 8;           // mu ring rows (rows Y-1..Y+4 live; a barrier
+                                           // separates their last reader from the next writer)
     R c1[NR * W];
     R c2[NR * W];
-    R mu1[NR * W];
-    R mu2[NR * W];
-    R mu3[NR * W];
-    R stash[2][2][18][W];             // [buffer][wave-2][population][lane]
+    R mu1[NM * MW];
+    R mu2[NM * MW];
+    R mu3[NM * MW];
+    R stash[2][2][18][kTileX];             // [buffer][wave-2][population][lane]
     R mt[kMatStride * (kMaxMaterials + 1)];
-    uint16_t nmask[NR * W];           // bit k-1: neighbour e_k solid; bit 8: node solid
+    uint16_t nmask[NM * MW];               // bit k-1: neighbour e_k solid; bit 8: node solid
     uint8_t m[NR * W];
 };
 
 __device__ __forceinline__ int ring_slot(int y, int y0) { return (y - y0 + 4) & 15; }
+__device__ __forceinline__ int mu_slot(int y, int y0) { return (y - y0 + 4) & 7; }
 
 // wrapped neighbourhood of (x, y) as 32-bit element offsets
 struct Nb32 {
@@ -493,13 +500,15 @@ __device__ __forceinline__ void pull_f(const Grid& g, const Consts<typename Tr<P
     }
 }
 
-// Chemical potentials of one mu-ring node and its solid-neighbour mask.
+// Chemical potentials of one mu-ring node (mu column mcol, c column
+// mcol + 1) and its solid-neighbour mask.
 template <int P>
 __device__ __forceinline__ void ring_mu(Ring<P>& sm, const Consts<typename Tr<P>::R>& c,
-                                        int y, int y0, int col) {
+                                        int y, int y0, int mcol) {
     using R = typename Tr<P>::R;
     using RG = Ring<P>;
     const int sc[3] = {ring_slot(y - 1, y0), ring_slot(y, y0), ring_slot(y + 1, y0)};
+    const int col = mcol + 1;
     const R* c1r[3];
     const R* c2r[3];
     const uint8_t* mr[3];
@@ -518,17 +527,15 @@ __device__ __forceinline__ void ring_mu(Ring<P>& sm, const Consts<typename Tr<P>
         if (mask == 0) {
             // bulk node: plain Laplacian (Eq. 20b)
             const R a1 = c1r[1][0], a2 = c2r[1][0], a3 = R(1) - a1 - a2;
-            R l1 = R(0), l2 = R(0), l3 = R(0);
+            R l1 = R(0), l2 = R(0);
 #pragma unroll
             for (int k = 1; k < 9; ++k) {
-                const R n1 = c1r[EY[k] + 1][EX[k]], n2 = c2r[EY[k] + 1][EX[k]];
-                l1 += wgt<R>(k) * (n1 - a1);
-                l2 += wgt<R>(k) * (n2 - a2);
-                l3 += wgt<R>(k) * ((R(1) - n1 - n2) - a3);
+                l1 += wgt<R>(k) * (c1r[EY[k] + 1][EX[k]] - a1);
+                l2 += wgt<R>(k) * (c2r[EY[k] + 1][EX[k]] - a2);
             }
             l1 *= R(6);
             l2 *= R(6);
-            l3 *= R(6);
+            const R l3 = -(l1 + l2);   // c3 = 1 - c1 - c2 at every node of the stencil
             const R tri = R(2) * c.lamT * a1 * a2 * (R(1) - a1 - a2);
             mu1 = c.k12D * (c.lam1 * a1 * (R(1) - a1) * (R(1) - R(2) * a1) - tri) - c.k34D * c.lam1 * l1;
             mu2 = c.k12D * (c.lam2 * a2 * (R(1) - a2) * (R(1) - R(2) * a2) - tri) - c.k34D * c.lam2 * l2;
@@ -537,7 +544,7 @@ __device__ __forceinline__ void ring_mu(Ring<P>& sm, const Consts<typename Tr<P>
             chem_pot<R>(c1r, c2r, mr, sm.mt, c, mu1, mu2, mu3);
         }
     }
-    const int o = sc[1] * RG::W + col;
+    const int o = mu_slot(y, y0) * RG::MW + mcol;
     sm.mu1[o] = mu1;
     sm.mu2[o] = mu2;
     sm.mu3[o] = mu3;
@@ -582,35 +589,49 @@ __device__ __forceinline__ void node_update(const Grid& g, const Consts<typename
                                                       int(o4), int(q * hstride), 0);
         }
     }
+    // The collision of Eq. 45 with the equilibria of Eqs. 2 and 4 and the
+    // sources of Eq. 11, regrouped into per-node scalars and vectors so that
+    // each direction k costs a few fused operations:
+    //   f'^i_k = (1 - 1/tau_i) f^i_k + w_k (P_i + e_k.V_i),  k != 0
+    //   P_i = eta_i mu_i / tau_i,  V_i = 3 (c_i u / tau_i + (1 - 1/(2 tau_i)) D_i)
+    //   g'_k = (1 - 1/tau_g) g_k + w_k (3 p / tau_g + e_k.G1 - G0)
+    //          + s_k (rho / tau_g + fsg (e_k.A - u.A))
+    //   A = grad rho + 3 (F_s + G),  G1 = 3 fsg (F_s + G) + 3 F_a,
+    //   G0 = 3 fsg u.(F_s + G),  fsg = 1 - 1/(2 tau_g)
     const R uu = o.ux * o.ux + o.uy * o.uy;
     const R em1 = c.eta1 * o.mu1, em2 = c.eta2 * o.mu2;
-    const R p3 = R(3) * o.p;
     const R fsg = R(1) - R(0.5) * o.itg;
+    const R om1 = R(1) - c.itau1, om2 = R(1) - c.itau2, omg = R(1) - o.itg;
+    const R P1 = c.itau1 * em1, P2 = c.itau2 * em2;
+    const R V1x = R(3) * (c.itau1 * o.c1 * o.ux + c.fs1 * d1x);
+    const R V1y = R(3) * (c.itau1 * o.c1 * o.uy + c.fs1 * d1y);
+    const R V2x = R(3) * (c.itau2 * o.c2 * o.ux + c.fs2 * d2x);
+    const R V2y = R(3) * (c.itau2 * o.c2 * o.uy + c.fs2 * d2y);
+    const R Ax = o.grx + R(3) * o.fx, Ay = o.gry + R(3) * o.fy;
+    const R uA = o.ux * Ax + o.uy * Ay;
+    const R G1x = R(3) * (fsg * o.fx + o.fax), G1y = R(3) * (fsg * o.fy + o.fay);
+    const R G0 = R(3) * fsg * (o.ux * o.fx + o.uy * o.fy);
+    const R Pg = R(3) * o.itg * o.p;
+    const R Rg = o.itg * o.rho;
     R g2[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
         const R w = wgt<R>(k);
         const R eu = R(EX[k]) * o.ux + R(EY[k]) * o.uy;
-        R fe1, fe2, ge;
-        const R sk = w * (R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu);  // Eq. 4
-        if (k == 0) {                                                    // Eqs. 2a, 2b
-            fe1 = o.c1 + (w - R(1)) * em1;
-            fe2 = o.c2 + (w - R(1)) * em2;
-            ge = p3 * (w - R(1)) + o.rho * sk;
+        const R sk = w * (eu * (R(3) + R(4.5) * eu) - R(1.5) * uu);       // Eq. 4
+        if (k == 0) {
+            f1[0] = om1 * f1[0] + c.itau1 * (o.c1 + (w - R(1)) * em1);
+            f2[0] = om2 * f2[0] + c.itau2 * (o.c2 + (w - R(1)) * em2);
+            g2[0] = omg * gg[0] + (w - R(1)) * Pg + sk * (Rg - fsg * uA) - w * G0;
         } else {
-            fe1 = w * (em1 + R(3) * o.c1 * eu);
-            fe2 = w * (em2 + R(3) * o.c2 * eu);
-            ge = p3 * w + o.rho * sk;
+            const R eV1 = R(EX[k]) * V1x + R(EY[k]) * V1y;
+            const R eV2 = R(EX[k]) * V2x + R(EY[k]) * V2y;
+            const R eA = R(EX[k]) * Ax + R(EY[k]) * Ay;
+            const R eG = R(EX[k]) * G1x + R(EY[k]) * G1y;
+            f1[k] = om1 * f1[k] + w * (P1 + eV1);
+            f2[k] = om2 * f2[k] + w * (P2 + eV2);
+            g2[k] = omg * gg[k] + w * (Pg + eG - G0) + sk * (Rg + fsg * (eA - uA));
         }
-        const R ed1 = R(EX[k]) * d1x + R(EY[k]) * d1y;                   // Eq. 11a
-        const R ed2 = R(EX[k]) * d2x + R(EY[k]) * d2y;
-        const R bx = sk * o.grx + (sk + w) * R(3) * o.fx;                // Eq. 11b
-        const R by = sk * o.gry + (sk + w) * R(3) * o.fy;
-        const R gk = fsg * ((R(EX[k]) - o.ux) * bx + (R(EY[k]) - o.uy) * by)
-                   + R(3) * w * (R(EX[k]) * o.fax + R(EY[k]) * o.fay);
-        f1[k] = f1[k] + (fe1 - f1[k]) * c.itau1 + c.fs1 * R(3) * w * ed1;  // Eq. 45
-        f2[k] = f2[k] + (fe2 - f2[k]) * c.itau2 + c.fs2 * R(3) * w * ed2;
-        g2[k] = gg[k] + (ge - gg[k]) * o.itg + gk;
         bst<P>(dst, c, 0, k, ob, o4, f1[k]);
         bst<P>(dst, c, 1, k, ob, o4, f2[k]);
         bst<P>(dst, c, 2, k, ob, o4, g2[k]);
@@ -632,34 +653,90 @@ __device__ __forceinline__ void node_update(const Grid& g, const Consts<typename
     }
 }
 
-template <int P, int H>
-__global__ __launch_bounds__(kThreads) void step_kernel(Grid g, Consts<typename Tr<P>::R> c,
-                                                        const uint8_t* __restrict__ mat,
-                                                        const double* __restrict__ mtab,
-                                                        PopBuf srcb, PopBuf dstb,
-                                                        typename Tr<P>::H* __restrict__ histp) {
+template <int P>
+__global__ __launch_bounds__(kStepThreads)
+__attribute__((amdgpu_waves_per_eu(P == P64 ? 2 : 4)))
+void step_kernel(Grid g, Consts<typename Tr<P>::R> c,
+                                                            const uint8_t* __restrict__ mat,
+                                                            const double* __restrict__ mtab,
+                                                            PopBuf srcb, PopBuf dstb,
+                                                            typename Tr<P>::H* __restrict__ histp) {
     using R = typename Tr<P>::R;
     using HT = typename Tr<P>::H;
     using RG = Ring<P>;
     __shared__ RG sm;
     const int t = tile_of(blockIdx.x, g.tiles_x * g.tiles_y);
-    const int x0 = (t % g.tiles_x) * kOut;
+    const int x0 = (t % g.tiles_x) * kTileX;
+    const int H = g.tile_rows;                             // strip height, a multiple of 4
     const int y0 = (t / g.tiles_x) * H;
     const int rows = g.ny - y0 < H ? g.ny - y0 : H;
     const int nit = (rows + 3) / 4;
     const int lane = threadIdx.x & (kTileX - 1);
     const int w = threadIdx.x / kTileX;
-    const int gxl = wrapc(x0 - 2 + lane, g.nx);            // this lane's column
-    const bool out_lane = lane >= 2 && lane < kTileX - 2 && x0 + lane - 2 < g.nx;
     const LatView<P> src = lat_view<P>(srcb, g.npad);
+    for (int i = threadIdx.x; i < kMatStride * (kMaxMaterials + 1); i += kStepThreads)
+        sm.mt[i] = R(mtab[i]);
+
+    // phase B of iteration it: mu on rows Y+1..Y+4, mu columns 0..65
+    auto phase_b = [&](int it) {
+        const int Y = y0 + 4 * it;
+        if (threadIdx.x < 4 * RG::MW) {
+            const int r = threadIdx.x / RG::MW;
+            const int mcol = threadIdx.x - r * RG::MW;
+            const int y = Y + 1 + r;
+            if (y >= y0 - 1) ring_mu<P>(sm, c, y, y0, mcol);  // prologue: rows below y0-1 lack neighbours
+        }
+    };
+
+    R nf1[9], nf2[9];
+    uint8_t nm;
+    if (w == 4) {
+        // ---- halo wave: lanes 0..15 own node (row Y+2+(lane>>2), column
+        //      x0-2, x0-1, x0+64, x0+65 for lane&3 = 0..3) of each iteration
+        const int hc = lane & 3;
+        const int ccol = hc < 2 ? hc : kTileX + hc;            // c ring column 0, 1, 66, 67
+        const int gx = wrapc(x0 - 2 + ccol, g.nx);
+        const int hr = (lane >> 2) & 3;
+        const bool act = lane < 16;
+        auto halo_a = [&](int it) {
+            const int Y = y0 + 4 * it;
+            R a = R(0), b = R(0);
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                a += nf1[k];
+                b += nf2[k];
+            }
+            if (act) {
+                const int sl = ring_slot(Y + 2 + hr, y0) * RG::W + ccol;
+                const bool fl = nm == 0;
+                sm.c1[sl] = fl ? a : R(0);
+                sm.c2[sl] = fl ? b : R(0);
+                sm.m[sl] = nm;
+            }
+            pull_f<P>(g, c, src, mat, gx, wrapc(Y + 6 + hr, g.ny), nf1, nf2, nm);
+        };
+        pull_f<P>(g, c, src, mat, gx, wrapc(y0 - 2 + hr, g.ny), nf1, nf2, nm);
+        halo_a(-1);
+        __syncthreads();
+        phase_b(-1);
+        __syncthreads();
+        halo_a(0);
+        for (int it = 0; it < nit; ++it) {
+            __syncthreads();
+            phase_b(it);
+            __syncthreads();
+            halo_a(it + 1);
+        }
+        return;
+    }
+
+    // ---- row waves
+    const int gxl = wrapc(x0 + lane, g.nx);                 // this lane's column
+    const bool out_lane = x0 + lane < g.nx;
     const LatView<P> dst = lat_view<P>(dstb, g.npad);
     const unsigned hstride = unsigned(g.npad * long(sizeof(HT)));
     const rsrc_t hist = make_rsrc(histp, 4u * hstride);
-    for (int i = threadIdx.x; i < kMatStride * (kMaxMaterials + 1); i += kThreads)
-        sm.mt[i] = R(mtab[i]);
-
-    R nf1[9], nf2[9], cf1[9], cf2[9], gg[9], ho[4];
-    uint8_t nm;
+    R cf1[9], cf2[9], gg[9], ho[4];
     Nb32 nb;
     unsigned idx = 0;
     int yo = 0;
@@ -668,7 +745,7 @@ __global__ __launch_bounds__(kThreads) void step_kernel(Grid g, Consts<typename 
     // the phase-C operands of iteration it, then the pulls for iteration it+1
     auto phase_a = [&](int it) {
         const int Y = y0 + 4 * it;
-        const int sl = ring_slot(Y + 2 + w, y0) * RG::W + lane;
+        const int sl = ring_slot(Y + 2 + w, y0) * RG::W + lane + 2;
         R a = R(0), b = R(0);
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
@@ -708,16 +785,6 @@ __global__ __launch_bounds__(kThreads) void step_kernel(Grid g, Consts<typename 
         pull_f<P>(g, c, src, mat, gxl, wrapc(Y + 6 + w, g.ny), nf1, nf2, nm);
         __builtin_amdgcn_sched_barrier(0);
     };
-    // phase B of iteration it: mu on rows Y+1..Y+4, ring columns 1..62
-    auto phase_b = [&](int it) {
-        const int Y = y0 + 4 * it;
-        if (threadIdx.x < 4 * (kTileX - 2)) {
-            const int r = threadIdx.x / (kTileX - 2);
-            const int col = threadIdx.x - r * (kTileX - 2) + 1;
-            const int y = Y + 1 + r;
-            if (y >= y0 - 1) ring_mu<P>(sm, c, y, y0, col);  // prologue: rows below y0-1 lack neighbours
-        }
-    };
 
     pull_f<P>(g, c, src, mat, gxl, wrapc(y0 - 2 + w, g.ny), nf1, nf2, nm);
     phase_a(-1);
@@ -733,16 +800,17 @@ __global__ __launch_bounds__(kThreads) void step_kernel(Grid g, Consts<typename 
         {
             Stencil<R> s;
             const int sl[3] = {ring_slot(yo - 1, y0), ring_slot(yo, y0), ring_slot(yo + 1, y0)};
+            const int ml[3] = {mu_slot(yo - 1, y0), mu_slot(yo, y0), mu_slot(yo + 1, y0)};
 #pragma unroll
             for (int r = 0; r < 3; ++r) {
-                s.c1[r] = &sm.c1[sl[r] * RG::W + lane];
-                s.c2[r] = &sm.c2[sl[r] * RG::W + lane];
-                s.m[r] = &sm.m[sl[r] * RG::W + lane];
-                s.mu1[r] = &sm.mu1[sl[r] * RG::W + lane];
-                s.mu2[r] = &sm.mu2[sl[r] * RG::W + lane];
+                s.c1[r] = &sm.c1[sl[r] * RG::W + lane + 2];
+                s.c2[r] = &sm.c2[sl[r] * RG::W + lane + 2];
+                s.m[r] = &sm.m[sl[r] * RG::W + lane + 2];
+                s.mu1[r] = &sm.mu1[ml[r] * RG::MW + lane + 1];
+                s.mu2[r] = &sm.mu2[ml[r] * RG::MW + lane + 1];
             }
-            s.mu3 = sm.mu3[sl[1] * RG::W + lane];
-            const unsigned mask = out_lane ? unsigned(sm.nmask[sl[1] * RG::W + lane]) : 256u;
+            s.mu3 = sm.mu3[ml[1] * RG::MW + lane + 1];
+            const unsigned mask = out_lane ? unsigned(sm.nmask[ml[1] * RG::MW + lane + 1]) : 256u;
             const bool live = out_lane && yo < y0 + rows && !(mask & 256u);
             if (w >= 2) {
 #pragma unroll
@@ -751,8 +819,8 @@ __global__ __launch_bounds__(kThreads) void step_kernel(Grid g, Consts<typename 
                     cf2[k] = sm.stash[(it - 1) & 1][w - 2][9 + k][lane];
                 }
             }
-            node_update<P>(g, c, s, sm.mt, nb, idx, live, mask, cf1, cf2, gg, ho, dst,
-                           hist, hstride);
+            node_update<P>(g, c, s, sm.mt, nb, idx, live, mask, cf1, cf2, gg, ho, dst, hist,
+                           hstride);
         }
         // phase A of the next iteration (after the last one it only issues
         // harmless in-range loads)
@@ -959,26 +1027,15 @@ __global__ __launch_bounds__(kThreads) void mass_final_kernel(const double* __re
 template <int P>
 using CT = Consts<typename Tr<P>::R>;
 
-template <int P, int TY>
-hipError_t step_ty(const Grid& g, const void* consts, const uint8_t* mat, const double* mtab,
-                   PopBuf src, PopBuf dst, void* hist, hipStream_t s) {
-    int nt = g.tiles_x * g.tiles_y;
-    hipLaunchKernelGGL((step_kernel<P, TY>), dim3(nt), dim3(kThreads), 0, s, g,
-                       *static_cast<const CT<P>*>(consts), mat, mtab, src, dst,
-                       static_cast<typename Tr<P>::H*>(hist));
-    return hipGetLastError();
-}
-
 template <int P>
 hipError_t step_p(const Grid& g, const void* consts, const uint8_t* mat, const double* mtab,
                   PopBuf src, PopBuf dst, void* hist, hipStream_t s) {
-    switch (g.tile_rows) {
-        case 16: return step_ty<P, 16>(g, consts, mat, mtab, src, dst, hist, s);
-        case 32: return step_ty<P, 32>(g, consts, mat, mtab, src, dst, hist, s);
-        case 64: return step_ty<P, 64>(g, consts, mat, mtab, src, dst, hist, s);
-        case 128: return step_ty<P, 128>(g, consts, mat, mtab, src, dst, hist, s);
-        default: return hipErrorInvalidValue;
-    }
+    if (g.tile_rows < 8 || g.tile_rows % 4) return hipErrorInvalidValue;
+    const int nt = g.tiles_x * g.tiles_y;
+    hipLaunchKernelGGL((step_kernel<P>), dim3(nt), dim3(kStepThreads), 0, s, g,
+                       *static_cast<const CT<P>*>(consts), mat, mtab, src, dst,
+                       static_cast<typename Tr<P>::H*>(hist));
+    return hipGetLastError();
 }
 
 constexpr int kAuxRows = 8;  // tile rows of the init / readout kernels
