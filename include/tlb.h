@@ -162,8 +162,40 @@ tlb_status tlb_time_steps(tlb_ctx* ctx, int64_t nsteps, double* ms_per_step);
  * rows: a multiple of 4 in [8, 4096]; default 64. */
 tlb_status tlb_set_tile_rows(tlb_ctx* ctx, int rows);
 
+/* Picks the strip height with the shortest step among candidate values
+ * (16 .. 128 rows, up to the lattice height) by timing steps_per_candidate
+ * steps of each, and keeps it.  The timed steps are real steps of the solve
+ * (results do not depend on the strip height), so the step count advances by
+ * steps_per_candidate times the number of candidates. */
+tlb_status tlb_autotune_rows(tlb_ctx* ctx, int steps_per_candidate, int* best_rows);
+
+/* ---- batches: many independent lattices advanced by shared launches ----
+ * A batch holds initialised contexts of one precision (any sizes, fluids and
+ * geometries).  Each step is one launch of the step kernel over the strips of
+ * all lattices, so small lattices fill the GPU together.  A lattice's result
+ * is bitwise the same alone or in any batch.  The caller owns the device
+ * table (tlb_batch_table_bytes, 256-byte aligned) and the contexts; while a
+ * context is in a batch it must not be stepped on its own (tlb_batch_step
+ * then returns TLB_ESTATE until tlb_batch_set is called again), and before a
+ * member is read or stepped on its own stream the batch stream must be
+ * synchronized (tlb_batch_sync).  Graph capture needs a non-default stream. */
+typedef struct tlb_batch tlb_batch;
+size_t     tlb_batch_table_bytes(int max_lattices);
+tlb_status tlb_batch_create(int max_lattices, void* dev_table, size_t bytes,
+                            void* hip_stream, tlb_batch** out);
+/* sets the member contexts (synchronizes their streams); n may be 0 */
+tlb_status tlb_batch_set(tlb_batch* batch, tlb_ctx* const* ctxs, int n);
+/* captures `steps` (even) launches into a HIP graph replayed by
+ * tlb_batch_step (0 = plain launches) */
+tlb_status tlb_batch_use_graph(tlb_batch* batch, int steps);
+/* advances every member by nsteps, asynchronously on the batch stream */
+tlb_status tlb_batch_step(tlb_batch* batch, int64_t nsteps);
+tlb_status tlb_batch_sync(tlb_batch* batch);
+const char* tlb_batch_last_error(const tlb_batch* batch);
+void       tlb_batch_destroy(tlb_batch* batch);
+
 /* Last error message of ctx, or of the calling thread's last failed
- * tlb_create / server call when ctx is NULL. */
+ * tlb_create / batch / server call when ctx is NULL. */
 const char* tlb_last_error(const tlb_ctx* ctx);
 
 /* Releases the context (not the caller's workspace).  NULL is a no-op. */

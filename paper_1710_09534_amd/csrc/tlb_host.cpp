@@ -29,7 +29,7 @@ struct Layout {
     size_t pop_bytes;   // one lattice (27 planes)
     size_t rest_off;    // P16: offset of the two FP32 rest planes inside a lattice
     size_t hist_bytes;
-    size_t off_pop[2], off_hist, off_mat, off_mtab, off_stage, off_part, off_result;
+    size_t off_pop[2], off_hist, off_mat, off_mtab, off_desc, off_stage, off_part, off_result;
     size_t total;
 };
 
@@ -50,6 +50,7 @@ Layout make_layout(int nx, int ny, int prec) {
     L.off_hist = o; o += L.hist_bytes;
     L.off_mat = o; o += align_up(L.npad, kAlign);
     L.off_mtab = o; o += align_up(kMatStride * (kMaxMaterials + 1) * sizeof(double), kAlign);
+    L.off_desc = o; o += kDescBytes;
     L.off_stage = o; o += align_up(size_t(27) * nx * ny * sizeof(double), kAlign);
     L.off_part = o; o += align_up(kReduceBlocks * 4 * sizeof(double), kAlign);
     L.off_result = o; o += kAlign;
@@ -78,6 +79,7 @@ struct tlb_ctx {
     int n_mats = 0;
     double mtab_host[kMatStride * (kMaxMaterials + 1)] = {};
     double* health = nullptr;  // pinned host copy of the last mass result
+    alignas(16) unsigned char desc_host[kDescBytes] = {};  // last uploaded descriptor
     bool health_pending = false;
     std::string err;
 };
@@ -147,6 +149,46 @@ void set_grid(tlb_ctx* c, int rows) {
     c->grid.tiles_x = (c->nx + kTileX - 1) / kTileX;   // 64-column strips
     c->grid.tiles_y = (c->ny + rows - 1) / rows;
 }
+
+// descriptor of ctx for the step kernel, with buf[cur] = current state at parity 0
+template <typename R, typename H>
+LatDesc<R, H> make_desc(tlb_ctx* c, const Consts<R>& k, int tile_begin, int cur) {
+    static_assert(sizeof(LatDesc<R, H>) <= kDescBytes, "descriptor slot too small");
+    LatDesc<R, H> d{};
+    d.g = c->grid;
+    d.c = k;
+    d.mat = reinterpret_cast<const uint8_t*>(c->ws + c->L.off_mat);
+    d.mtab = reinterpret_cast<const double*>(c->ws + c->L.off_mtab);
+    d.buf[0] = popbuf(c, 0);
+    d.buf[1] = popbuf(c, 1);
+    d.hist = reinterpret_cast<H*>(c->ws + c->L.off_hist);
+    d.tile_begin = tile_begin;
+    d.cur = cur;
+    return d;
+}
+
+// writes ctx's descriptor (tile_begin 0, cur 0) into host buffer `out`
+size_t fill_desc(tlb_ctx* c, void* out, int tile_begin, int cur) {
+    if (c->prec == P64) {
+        auto d = make_desc<double, double>(c, c->c64, tile_begin, cur);
+        std::memcpy(out, &d, sizeof(d));
+        return sizeof(d);
+    }
+    auto d = make_desc<float, float>(c, c->c32, tile_begin, cur);
+    std::memcpy(out, &d, sizeof(d));
+    return sizeof(d);
+}
+
+tlb_status upload_desc(tlb_ctx* c) {
+    size_t n = fill_desc(c, c->desc_host, 0, 0);
+    hipError_t e = hipMemcpyAsync(c->ws + c->L.off_desc, c->desc_host, n, hipMemcpyHostToDevice,
+                                  c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return dev_fail(c, e, "descriptor upload");
+    return TLB_OK;
+}
+
+int ntiles(const tlb_ctx* c) { return c->grid.tiles_x * c->grid.tiles_y; }
 
 tlb_status run_mass(tlb_ctx* c) {
     hipError_t e = launch_mass(c->prec, c->grid, consts_ptr(c),
@@ -339,15 +381,12 @@ tlb_status tlb_init_fields(tlb_ctx* c, const double* c1, const double* c2, const
     c->inited = true;
     c->diverged = false;
     c->health_pending = false;
-    return TLB_OK;
+    return upload_desc(c);
 }
 
 static tlb_status step_impl(tlb_ctx* c, int64_t nsteps, bool checks) {
     for (int64_t s = 0; s < nsteps; ++s) {
-        hipError_t e = launch_step(c->prec, c->grid, consts_ptr(c),
-                                   reinterpret_cast<uint8_t*>(c->ws + c->L.off_mat),
-                                   reinterpret_cast<double*>(c->ws + c->L.off_mtab),
-                                   popbuf(c, c->cur), popbuf(c, 1 - c->cur), c->ws + c->L.off_hist,
+        hipError_t e = launch_step(c->prec, c->ws + c->L.off_desc, 1, ntiles(c), c->cur,
                                    c->stream);
         if (e != hipSuccess) return dev_fail(c, e, "step kernel");
         c->cur = 1 - c->cur;
@@ -386,7 +425,7 @@ tlb_status tlb_set_tile_rows(tlb_ctx* c, int rows) {
     if (!c || rows < 8 || rows > 4096 || rows % 4)
         return fail(c, TLB_EINVAL, "strip rows must be a multiple of 4 in [8, 4096]");
     set_grid(c, rows);
-    return TLB_OK;
+    return c->inited ? upload_desc(c) : TLB_OK;
 }
 
 tlb_status tlb_read_fields(tlb_ctx* c, uint32_t mask, double* out) {
@@ -500,7 +539,7 @@ tlb_status tlb_checkpoint_load(tlb_ctx* c, const void* buf) {
     c->inited = true;
     c->diverged = false;
     c->health_pending = false;
-    return TLB_OK;
+    return upload_desc(c);
 }
 
 tlb_status tlb_time_steps(tlb_ctx* c, int64_t nsteps, double* ms) {
@@ -520,6 +559,204 @@ tlb_status tlb_time_steps(tlb_ctx* c, int64_t nsteps, double* ms) {
     if (st != TLB_OK) return st;
     if (e != hipSuccess) return dev_fail(c, e, "time_steps");
     *ms = double(t) / double(nsteps);
+    return TLB_OK;
+}
+
+// ------------------------------------------------------------------ batches
+}  // extern "C"
+
+struct tlb_batch {
+    char* dev;            // caller-owned device table (kDescBytes per lattice)
+    size_t bytes;
+    int cap;
+    hipStream_t stream;
+    int prec = -1;
+    std::vector<tlb_ctx*> ctxs;
+    std::vector<int> base_cur;         // each member's cur when the table was written
+    std::vector<unsigned char> host;   // staged table
+    int total_tiles = 0;
+    int parity = 0;                    // parity of the next step relative to the table
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int graph_steps = 0;
+    std::string err;
+};
+
+namespace {
+tlb_status bfail(tlb_batch* b, tlb_status s, const std::string& m) {
+    if (b) b->err = m;
+    g_last_error = m;
+    return s;
+}
+void drop_graph(tlb_batch* b) {
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->graph_steps = 0;
+}
+}  // namespace
+
+extern "C" {
+
+size_t tlb_batch_table_bytes(int max_lattices) {
+    return max_lattices > 0 ? size_t(max_lattices) * kDescBytes : 0;
+}
+
+tlb_status tlb_batch_create(int max_lattices, void* dev_table, size_t bytes, void* hip_stream,
+                            tlb_batch** out) {
+    if (!out) return bfail(nullptr, TLB_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (max_lattices <= 0 || !dev_table || bytes < tlb_batch_table_bytes(max_lattices))
+        return bfail(nullptr, TLB_EINVAL, "bad batch capacity or table");
+    if (reinterpret_cast<uintptr_t>(dev_table) % kAlign)
+        return bfail(nullptr, TLB_EINVAL, "table not 256-byte aligned");
+    tlb_batch* b = new tlb_batch();
+    b->dev = static_cast<char*>(dev_table);
+    b->bytes = bytes;
+    b->cap = max_lattices;
+    b->stream = static_cast<hipStream_t>(hip_stream);
+    *out = b;
+    return TLB_OK;
+}
+
+tlb_status tlb_batch_set(tlb_batch* b, tlb_ctx* const* ctxs, int n) {
+    if (!b || (n > 0 && !ctxs) || n < 0) return bfail(b, TLB_EINVAL, "null batch or contexts");
+    if (n > b->cap) return bfail(b, TLB_EINVAL, "more lattices than the batch capacity");
+    int prec = -1, tiles = 0;
+    for (int i = 0; i < n; ++i) {
+        tlb_ctx* c = ctxs[i];
+        if (!c) return bfail(b, TLB_EINVAL, "null context in batch");
+        if (!c->inited) return bfail(b, TLB_ESTATE, "every context must be initialised");
+        if (c->diverged) return bfail(b, TLB_EDIVERGED, "a context has diverged");
+        if (prec >= 0 && c->prec != prec) return bfail(b, TLB_EINVAL, "mixed precisions in batch");
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == c) return bfail(b, TLB_EINVAL, "context listed twice");
+        prec = c->prec;
+        tiles += ntiles(c);
+    }
+    // finish pending work of the contexts on their own streams first
+    for (int i = 0; i < n; ++i)
+        if (hipStreamSynchronize(ctxs[i]->stream) != hipSuccess)
+            return bfail(b, TLB_EDEVICE, "context stream sync failed");
+    b->host.assign(size_t(n > 0 ? n : 1) * kDescBytes, 0);
+    int begin = 0;
+    for (int i = 0; i < n; ++i) {
+        fill_desc(ctxs[i], b->host.data() + size_t(i) * kDescBytes, begin, ctxs[i]->cur);
+        begin += ntiles(ctxs[i]);
+    }
+    if (n > 0) {
+        hipError_t e = hipMemcpyAsync(b->dev, b->host.data(), size_t(n) * kDescBytes,
+                                      hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+        if (e != hipSuccess) return bfail(b, TLB_EDEVICE, std::string("batch table upload: ") + hipGetErrorString(e));
+    }
+    drop_graph(b);
+    b->ctxs.assign(ctxs, ctxs + n);
+    b->base_cur.resize(size_t(n));
+    for (int i = 0; i < n; ++i) b->base_cur[size_t(i)] = ctxs[i]->cur;
+    b->prec = prec;
+    b->total_tiles = tiles;
+    b->parity = 0;
+    return TLB_OK;
+}
+
+// records `steps` (even) step launches starting at parity 0 into a graph
+tlb_status tlb_batch_use_graph(tlb_batch* b, int steps) {
+    if (!b || steps < 0 || (steps & 1)) return bfail(b, TLB_EINVAL, "graph steps must be even and >= 0");
+    drop_graph(b);
+    if (steps == 0 || b->ctxs.empty()) return TLB_OK;
+    hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return bfail(b, TLB_EDEVICE, std::string("begin capture: ") + hipGetErrorString(e));
+    hipError_t le = hipSuccess;
+    for (int s = 0; s < steps && le == hipSuccess; ++s)
+        le = launch_step(b->prec, b->dev, int(b->ctxs.size()), b->total_tiles, s & 1, b->stream);
+    e = hipStreamEndCapture(b->stream, &b->graph);
+    if (le != hipSuccess || e != hipSuccess) {
+        drop_graph(b);
+        return bfail(b, TLB_EDEVICE, "graph capture failed");
+    }
+    e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        drop_graph(b);
+        return bfail(b, TLB_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    b->graph_steps = steps;
+    return TLB_OK;
+}
+
+tlb_status tlb_batch_step(tlb_batch* b, int64_t nsteps) {
+    if (!b || nsteps < 0) return bfail(b, TLB_EINVAL, "null batch or negative steps");
+    if (b->ctxs.empty() || nsteps == 0) return TLB_OK;
+    for (size_t i = 0; i < b->ctxs.size(); ++i) {
+        const tlb_ctx* c = b->ctxs[i];
+        if (c->diverged) return bfail(b, TLB_EDIVERGED, "a context has diverged");
+        if (((b->base_cur[i] + b->parity) & 1) != c->cur)
+            return bfail(b, TLB_ESTATE, "a member was stepped outside the batch: call tlb_batch_set");
+    }
+    int64_t done = 0;
+    const int nd = int(b->ctxs.size());
+    while (done < nsteps) {
+        hipError_t e;
+        if (b->exec && (b->parity & 1) == 0 && nsteps - done >= b->graph_steps) {
+            e = hipGraphLaunch(b->exec, b->stream);
+            if (e != hipSuccess) return bfail(b, TLB_EDEVICE, std::string("graph launch: ") + hipGetErrorString(e));
+            done += b->graph_steps;
+            continue;   // even step count: parity unchanged
+        }
+        e = launch_step(b->prec, b->dev, nd, b->total_tiles, b->parity, b->stream);
+        if (e != hipSuccess) return bfail(b, TLB_EDEVICE, std::string("batch step: ") + hipGetErrorString(e));
+        b->parity ^= 1;
+        ++done;
+    }
+    for (tlb_ctx* c : b->ctxs) {
+        c->cur ^= int(nsteps & 1);
+        c->steps += nsteps;
+    }
+    return TLB_OK;
+}
+
+tlb_status tlb_batch_sync(tlb_batch* b) {
+    if (!b) return bfail(b, TLB_EINVAL, "null batch");
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return bfail(b, TLB_EDEVICE, std::string("batch sync: ") + hipGetErrorString(e));
+    return TLB_OK;
+}
+
+const char* tlb_batch_last_error(const tlb_batch* b) {
+    return b ? b->err.c_str() : g_last_error.c_str();
+}
+
+void tlb_batch_destroy(tlb_batch* b) {
+    if (!b) return;
+    hipStreamSynchronize(b->stream);
+    drop_graph(b);
+    delete b;
+}
+
+// ---------------------------------------------------------------- autotuner
+tlb_status tlb_autotune_rows(tlb_ctx* c, int steps_per_candidate, int* best_rows) {
+    if (!c || steps_per_candidate <= 0) return fail(c, TLB_EINVAL, "bad arguments");
+    if (!c->inited) return fail(c, TLB_ESTATE, "init_fields must precede autotune");
+    static const int cand[] = {16, 24, 32, 48, 64, 96, 128};
+    int best = c->grid.tile_rows;
+    double best_ms = 1e30;
+    const int limit = ((c->ny + 3) / 4) * 4;
+    for (int rows : cand) {
+        if (rows > (limit < 16 ? 16 : limit)) break;
+        tlb_status st = tlb_set_tile_rows(c, rows);
+        if (st != TLB_OK) return st;
+        double ms = 0.0;
+        st = tlb_time_steps(c, steps_per_candidate, &ms);
+        if (st != TLB_OK) return st;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = rows;
+        }
+    }
+    tlb_status st = tlb_set_tile_rows(c, best);
+    if (st != TLB_OK) return st;
+    if (best_rows) *best_rows = best;
     return TLB_OK;
 }
 

@@ -52,12 +52,30 @@ struct Grid {
     int tiles_x, tiles_y, tile_rows;
 };
 
+// Device descriptor of one lattice for the step kernel (R: arithmetic type,
+// H: history storage type).  buf[cur] holds the current state at the step
+// the launch's parity 0 refers to.
+template <typename R, typename H>
+struct LatDesc {
+    Grid g;
+    Consts<R> c;
+    const uint8_t* mat;
+    const double* mtab;
+    PopBuf buf[2];
+    H* hist;
+    int tile_begin;   // prefix sum of the strip counts of the preceding lattices
+    int cur;
+};
+// A descriptor table stores descriptor i at byte offset i * kDescBytes.
+constexpr size_t kDescBytes = 512;  // >= sizeof(LatDesc), a multiple of 256
+
 // host-side launchers (tlb_kernels.hip)
+// Step kernel over a device table of descriptors (LatDesc<double,double> for
+// P64, LatDesc<float,float> otherwise); total_tiles = sum of strip counts.
+hipError_t launch_step(int prec, const void* descs, int ndesc, int total_tiles, int parity,
+                       hipStream_t s);
 // `consts` points to a host Consts<double> (P64) or Consts<float> (P32, P16);
 // `mtab` to the device material table.
-hipError_t launch_step(int prec, const Grid& g, const void* consts, const uint8_t* mat,
-                       const double* mtab, PopBuf src, PopBuf dst, void* hist,
-                       hipStream_t s);
 hipError_t launch_init(int prec, const Grid& g, const void* consts, const uint8_t* mat,
                        const double* mtab, const double* in4, PopBuf dst, void* hist,
                        hipStream_t s);

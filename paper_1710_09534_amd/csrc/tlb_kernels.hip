@@ -653,19 +653,16 @@ __device__ __forceinline__ void node_update(const Grid& g, const Consts<typename
     }
 }
 
+// One strip (tile t) of one lattice.
 template <int P>
-__global__ __launch_bounds__(kStepThreads)
-__attribute__((amdgpu_waves_per_eu(P == P64 ? 2 : 4)))
-void step_kernel(Grid g, Consts<typename Tr<P>::R> c,
-                                                            const uint8_t* __restrict__ mat,
-                                                            const double* __restrict__ mtab,
-                                                            PopBuf srcb, PopBuf dstb,
-                                                            typename Tr<P>::H* __restrict__ histp) {
+__device__ __forceinline__ void step_tile(const Grid& g, const Consts<typename Tr<P>::R>& c,
+                                          const uint8_t* __restrict__ mat,
+                                          const double* __restrict__ mtab, PopBuf srcb,
+                                          PopBuf dstb, typename Tr<P>::H* __restrict__ histp,
+                                          int t, Ring<P>& sm) {
     using R = typename Tr<P>::R;
     using HT = typename Tr<P>::H;
     using RG = Ring<P>;
-    __shared__ RG sm;
-    const int t = tile_of(blockIdx.x, g.tiles_x * g.tiles_y);
     const int x0 = (t % g.tiles_x) * kTileX;
     const int H = g.tile_rows;                             // strip height, a multiple of 4
     const int y0 = (t / g.tiles_x) * H;
@@ -826,6 +823,38 @@ void step_kernel(Grid g, Consts<typename Tr<P>::R> c,
         // harmless in-range loads)
         phase_a(it + 1);
     }
+}
+
+// The step kernel: workgroups enumerate the strips of a table of lattices
+// (one lattice, or a batch of independent lattices of any sizes and fluid
+// parameters sharing one precision).  The table's tile_begin fields are the
+// prefix sums of the lattices' strip counts; a workgroup finds its lattice by
+// binary search.  parity selects which of each lattice's two population
+// buffers is the source in this step.  A lattice's strips are computed by the
+// same code whatever else is in the table, so results do not depend on the
+// batch.
+template <int P>
+__global__ __launch_bounds__(kStepThreads)
+__attribute__((amdgpu_waves_per_eu(P == P64 ? 2 : 4)))
+void step_kernel(const unsigned char* __restrict__ descs, int ndesc, int total_tiles, int parity) {
+    using D = LatDesc<typename Tr<P>::R, typename Tr<P>::H>;
+    // descriptors sit kDescBytes apart (not sizeof(D) apart)
+    auto desc = [&](int i) -> const D& {
+        return *reinterpret_cast<const D*>(descs + size_t(i) * kDescBytes);
+    };
+    __shared__ Ring<P> sm;
+    const int L = tile_of(blockIdx.x, total_tiles);
+    int lo = 0, hi = ndesc - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (desc(mid).tile_begin <= L) lo = mid;
+        else hi = mid - 1;
+    }
+    const D& d = desc(lo);
+    const Grid g = d.g;
+    const Consts<typename Tr<P>::R> c = d.c;
+    const int sb = (d.cur + parity) & 1;
+    step_tile<P>(g, c, d.mat, d.mtab, d.buf[sb], d.buf[sb ^ 1], d.hist, L - d.tile_begin, sm);
 }
 
 // ------------------------------------------------------------------- init
@@ -1028,13 +1057,9 @@ template <int P>
 using CT = Consts<typename Tr<P>::R>;
 
 template <int P>
-hipError_t step_p(const Grid& g, const void* consts, const uint8_t* mat, const double* mtab,
-                  PopBuf src, PopBuf dst, void* hist, hipStream_t s) {
-    if (g.tile_rows < 8 || g.tile_rows % 4) return hipErrorInvalidValue;
-    const int nt = g.tiles_x * g.tiles_y;
-    hipLaunchKernelGGL((step_kernel<P>), dim3(nt), dim3(kStepThreads), 0, s, g,
-                       *static_cast<const CT<P>*>(consts), mat, mtab, src, dst,
-                       static_cast<typename Tr<P>::H*>(hist));
+hipError_t step_p(const void* descs, int ndesc, int total_tiles, int parity, hipStream_t s) {
+    hipLaunchKernelGGL((step_kernel<P>), dim3(total_tiles), dim3(kStepThreads), 0, s,
+                       static_cast<const unsigned char*>(descs), ndesc, total_tiles, parity);
     return hipGetLastError();
 }
 
@@ -1042,13 +1067,12 @@ constexpr int kAuxRows = 8;  // tile rows of the init / readout kernels
 
 }  // namespace
 
-hipError_t launch_step(int prec, const Grid& g, const void* consts, const uint8_t* mat,
-                       const double* mtab, PopBuf src, PopBuf dst, void* hist,
+hipError_t launch_step(int prec, const void* descs, int ndesc, int total_tiles, int parity,
                        hipStream_t s) {
     switch (prec) {
-        case P64: return step_p<P64>(g, consts, mat, mtab, src, dst, hist, s);
-        case P32: return step_p<P32>(g, consts, mat, mtab, src, dst, hist, s);
-        case P16: return step_p<P16>(g, consts, mat, mtab, src, dst, hist, s);
+        case P64: return step_p<P64>(descs, ndesc, total_tiles, parity, s);
+        case P32: return step_p<P32>(descs, ndesc, total_tiles, parity, s);
+        case P16: return step_p<P16>(descs, ndesc, total_tiles, parity, s);
         default: return hipErrorInvalidValue;
     }
 }

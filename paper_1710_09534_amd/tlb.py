@@ -65,6 +65,15 @@ _SIGS = {
     "tlb_checkpoint_load": (C.c_int, [_vp, _vp]),
     "tlb_time_steps": (C.c_int, [_vp, C.c_int64, _D]),
     "tlb_set_tile_rows": (C.c_int, [_vp, C.c_int]),
+    "tlb_autotune_rows": (C.c_int, [_vp, C.c_int, C.POINTER(C.c_int)]),
+    "tlb_batch_table_bytes": (C.c_size_t, [C.c_int]),
+    "tlb_batch_create": (C.c_int, [C.c_int, _vp, C.c_size_t, _vp, C.POINTER(_vp)]),
+    "tlb_batch_set": (C.c_int, [_vp, C.POINTER(_vp), C.c_int]),
+    "tlb_batch_use_graph": (C.c_int, [_vp, C.c_int]),
+    "tlb_batch_step": (C.c_int, [_vp, C.c_int64]),
+    "tlb_batch_sync": (C.c_int, [_vp]),
+    "tlb_batch_last_error": (C.c_char_p, [_vp]),
+    "tlb_batch_destroy": (None, [_vp]),
     "tlb_last_error": (C.c_char_p, [_vp]),
     "tlb_destroy": (None, [_vp]),
 }
@@ -216,6 +225,54 @@ class Solver:
         ms = C.c_double()
         _check(lib.tlb_time_steps(self.ctx, int(n), C.byref(ms)), self.ctx)
         return ms.value
+
+    def autotune_rows(self, steps_per_candidate: int = 20) -> int:
+        best = C.c_int()
+        _check(lib.tlb_autotune_rows(self.ctx, int(steps_per_candidate), C.byref(best)), self.ctx)
+        return best.value
+
+
+class Batch:
+    """Independent lattices advanced by shared step launches (tlb_batch_*)."""
+
+    def __init__(self, max_lattices: int, device="cuda:0", stream=None):
+        import torch
+        nbytes = int(lib.tlb_batch_table_bytes(int(max_lattices)))
+        self.table = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        # a stream of its own (default priority): graph capture needs a
+        # non-default stream; call sync() before using members on their own
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
+        h = _vp()
+        st = lib.tlb_batch_create(int(max_lattices), _vp(self.table.data_ptr()), nbytes,
+                                  _vp(self.stream.cuda_stream), C.byref(h))
+        if st != TLB_OK:
+            raise TlbError(st, lib.tlb_batch_last_error(None).decode())
+        self.h = h
+        self.members = []
+
+    def _check(self, st):
+        if st != TLB_OK:
+            raise TlbError(st, lib.tlb_batch_last_error(self.h).decode())
+
+    def set(self, solvers):
+        arr = (_vp * max(1, len(solvers)))(*[s.ctx for s in solvers])
+        self._check(lib.tlb_batch_set(self.h, arr, len(solvers)))
+        self.members = list(solvers)
+
+    def use_graph(self, steps: int):
+        self._check(lib.tlb_batch_use_graph(self.h, int(steps)))
+
+    def step(self, n: int):
+        self._check(lib.tlb_batch_step(self.h, int(n)))
+
+    def sync(self):
+        self._check(lib.tlb_batch_sync(self.h))
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            lib.tlb_batch_destroy(h)
+            self.h = None
 
 
 def from_problem(problem: dict, precision="fp64", device="cuda:0", init=True) -> Solver:
