@@ -194,8 +194,65 @@ tlb_status tlb_batch_sync(tlb_batch* batch);
 const char* tlb_batch_last_error(const tlb_batch* batch);
 void       tlb_batch_destroy(tlb_batch* batch);
 
+/* ---- serving: continuous batching of independent solves ----
+ * A server owns a worker thread that admits submitted requests (in arrival
+ * order, skipping ones that do not fit yet) whenever one of max_slots slots
+ * and a block of the caller's device arena are free, keeps their populations
+ * resident, and advances all running requests together with the batched step
+ * kernel, quantum_steps at a time (a quantum also ends at the next
+ * completion).  Finished requests are checked for NaN/Inf (a diverged request
+ * fails alone), read out to host memory and release their memory for waiting
+ * requests.  A request's result is bitwise the same alone or in any mix.
+ * Time to solution = completion - submission (host steady clock). */
+enum { TLB_REQ_QUEUED = 0, TLB_REQ_RUNNING = 1, TLB_REQ_DONE = 2, TLB_REQ_FAILED = 3,
+       TLB_REQ_CANCELLED = 4 };
+
+typedef struct {
+    int nx, ny;
+    tlb_fluid fluid;
+    int periodic_x, periodic_y;
+    const uint8_t* material;          /* [ny*nx], 0 = fluid, m = mats[m-1] */
+    const tlb_material* mats;
+    int n_mats;
+    const double *c1, *c2, *ux, *uy;  /* [ny*nx]; ux, uy nullable */
+    int64_t nsteps;
+    uint32_t result_fields;           /* TLB_F_* fields kept for tlb_server_result */
+} tlb_request;                        /* every array is copied by tlb_server_submit */
+
+typedef struct {
+    int64_t completed, failed, queued, running;
+    double busy_seconds;              /* time spent in device quanta */
+    double node_steps;                /* lattice updates performed */
+    size_t arena_free_largest;        /* largest free arena block (bytes) */
+} tlb_server_counters;
+
+typedef struct tlb_server tlb_server;
+/* dev_arena: caller-owned device memory (256-byte aligned) that bounds the
+ * server's device footprint (the HBM budget); the server never allocates
+ * device memory of its own.  hip_stream: the server's stream (non-default). */
+tlb_status tlb_server_create(void* dev_arena, size_t arena_bytes, int max_slots,
+                             tlb_precision p, int64_t quantum_steps, void* hip_stream,
+                             tlb_server** out);
+/* TLB_ENOMEM if the request can never fit the arena */
+tlb_status tlb_server_submit(tlb_server* s, const tlb_request* req, uint64_t* id);
+tlb_status tlb_server_poll(tlb_server* s, uint64_t id, int* state);
+/* blocks until the request is DONE, FAILED or CANCELLED (timeout_s < 0:
+ * no limit; TLB_EBUSY on timeout) */
+tlb_status tlb_server_wait(tlb_server* s, uint64_t id, double timeout_s);
+/* fields (bit order, subset of result_fields) and time to solution */
+tlb_status tlb_server_result(tlb_server* s, uint64_t id, uint32_t field_mask,
+                             double* host_out, double* latency_s);
+/* forgets a finished request (frees its host result) */
+tlb_status tlb_server_release(tlb_server* s, uint64_t id);
+/* queued: dropped; running: leaves at the next quantum boundary */
+tlb_status tlb_server_cancel(tlb_server* s, uint64_t id);
+tlb_status tlb_server_stats(tlb_server* s, tlb_server_counters* out);
+const char* tlb_server_last_error(const tlb_server* s);
+/* stops the worker (running and queued requests are cancelled) */
+void       tlb_server_destroy(tlb_server* s);
+
 /* Last error message of ctx, or of the calling thread's last failed
- * tlb_create / batch / server call when ctx is NULL. */
+ * tlb_create / batch call when ctx is NULL. */
 const char* tlb_last_error(const tlb_ctx* ctx);
 
 /* Releases the context (not the caller's workspace).  NULL is a no-op. */

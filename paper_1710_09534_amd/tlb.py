@@ -44,6 +44,23 @@ class tlb_material(C.Structure):
                 ("wall_u", C.c_double * 2)]
 
 
+class tlb_request(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("fluid", tlb_fluid),
+                ("periodic_x", C.c_int), ("periodic_y", C.c_int),
+                ("material", C.POINTER(C.c_uint8)), ("mats", C.POINTER(tlb_material)),
+                ("n_mats", C.c_int), ("c1", C.POINTER(C.c_double)), ("c2", C.POINTER(C.c_double)),
+                ("ux", C.POINTER(C.c_double)), ("uy", C.POINTER(C.c_double)),
+                ("nsteps", C.c_int64), ("result_fields", C.c_uint32)]
+
+
+class tlb_server_counters(C.Structure):
+    _fields_ = [("completed", C.c_int64), ("failed", C.c_int64), ("queued", C.c_int64),
+                ("running", C.c_int64), ("busy_seconds", C.c_double),
+                ("node_steps", C.c_double), ("arena_free_largest", C.c_size_t)]
+
+
+TLB_REQ_QUEUED, TLB_REQ_RUNNING, TLB_REQ_DONE, TLB_REQ_FAILED, TLB_REQ_CANCELLED = range(5)
+
 lib = C.CDLL(LIB_PATH)
 _vp = C.c_void_p
 _D = C.POINTER(C.c_double)
@@ -74,6 +91,17 @@ _SIGS = {
     "tlb_batch_sync": (C.c_int, [_vp]),
     "tlb_batch_last_error": (C.c_char_p, [_vp]),
     "tlb_batch_destroy": (None, [_vp]),
+    "tlb_server_create": (C.c_int, [_vp, C.c_size_t, C.c_int, C.c_int, C.c_int64, _vp,
+                                    C.POINTER(_vp)]),
+    "tlb_server_submit": (C.c_int, [_vp, C.POINTER(tlb_request), C.POINTER(C.c_uint64)]),
+    "tlb_server_poll": (C.c_int, [_vp, C.c_uint64, C.POINTER(C.c_int)]),
+    "tlb_server_wait": (C.c_int, [_vp, C.c_uint64, C.c_double]),
+    "tlb_server_result": (C.c_int, [_vp, C.c_uint64, C.c_uint32, _D, _D]),
+    "tlb_server_release": (C.c_int, [_vp, C.c_uint64]),
+    "tlb_server_cancel": (C.c_int, [_vp, C.c_uint64]),
+    "tlb_server_stats": (C.c_int, [_vp, C.POINTER(tlb_server_counters)]),
+    "tlb_server_last_error": (C.c_char_p, [_vp]),
+    "tlb_server_destroy": (None, [_vp]),
     "tlb_last_error": (C.c_char_p, [_vp]),
     "tlb_destroy": (None, [_vp]),
 }
@@ -282,3 +310,98 @@ def from_problem(problem: dict, precision="fp64", device="cuda:0", init=True) ->
     if init:
         s.init_fields(problem["c1"], problem["c2"], problem.get("ux"), problem.get("uy"))
     return s
+
+
+class Server:
+    """Continuous-batching solve server (tlb_server_*).  The arena (a torch
+    uint8 tensor of arena_bytes) is the server's whole device budget."""
+
+    def __init__(self, arena_bytes: int, max_slots: int, precision="fp32", quantum=200,
+                 device="cuda:0"):
+        import torch
+        self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device)
+        self.stream = torch.cuda.Stream(device=device)
+        h = _vp()
+        st = lib.tlb_server_create(_vp(self.arena.data_ptr()), int(arena_bytes), int(max_slots),
+                                   self.precision, int(quantum), _vp(self.stream.cuda_stream),
+                                   C.byref(h))
+        if st != TLB_OK:
+            raise TlbError(st, lib.tlb_server_last_error(None).decode())
+        self.h = h
+
+    def _check(self, st):
+        if st != TLB_OK:
+            raise TlbError(st, lib.tlb_server_last_error(self.h).decode())
+
+    def submit(self, problem: dict, nsteps: int, fields: int = F_ALL) -> int:
+        nx, ny = int(problem["nx"]), int(problem["ny"])
+        keep = []
+
+        def arr(a, dtype=np.float64):
+            if a is None:
+                return None
+            a = np.ascontiguousarray(a, dtype=dtype)
+            assert a.shape == (ny, nx)
+            keep.append(a)
+            return a
+
+        mat = arr(problem["material"], np.uint8)
+        c1, c2 = arr(problem["c1"]), arr(problem["c2"])
+        ux, uy = arr(problem.get("ux")), arr(problem.get("uy"))
+        mats = make_materials(problem["mats"])
+        r = tlb_request()
+        r.nx, r.ny = nx, ny
+        r.fluid = make_fluid(problem["fluid"])
+        px, py = problem.get("periodic", (1, 1))
+        r.periodic_x, r.periodic_y = int(px), int(py)
+        r.material = mat.ctypes.data_as(C.POINTER(C.c_uint8))
+        r.mats = mats
+        r.n_mats = len(problem["mats"])
+        r.c1, r.c2 = _dp(c1), _dp(c2)
+        r.ux, r.uy = _dp(ux), _dp(uy)
+        r.nsteps = int(nsteps)
+        r.result_fields = int(fields)
+        rid = C.c_uint64()
+        self._check(lib.tlb_server_submit(self.h, C.byref(r), C.byref(rid)))
+        return rid.value
+
+    def poll(self, rid: int) -> int:
+        st = C.c_int()
+        self._check(lib.tlb_server_poll(self.h, rid, C.byref(st)))
+        return st.value
+
+    def wait(self, rid: int, timeout: float = -1.0):
+        self._check(lib.tlb_server_wait(self.h, rid, float(timeout)))
+
+    def result(self, rid: int, nx: int, ny: int, mask: int = F_ALL):
+        names = [f for i, f in enumerate(FIELDS) if mask & (1 << i)]
+        out = np.zeros((len(names), ny, nx))
+        lat = C.c_double()
+        self._check(lib.tlb_server_result(self.h, rid, mask, _dp(out), C.byref(lat)))
+        return {k: out[i] for i, k in enumerate(names)}, lat.value
+
+    def latency(self, rid: int) -> float:
+        lat = C.c_double()
+        self._check(lib.tlb_server_result(self.h, rid, 0, None, C.byref(lat)))
+        return lat.value
+
+    def release(self, rid: int):
+        self._check(lib.tlb_server_release(self.h, rid))
+
+    def cancel(self, rid: int):
+        self._check(lib.tlb_server_cancel(self.h, rid))
+
+    def stats(self) -> dict:
+        c = tlb_server_counters()
+        self._check(lib.tlb_server_stats(self.h, C.byref(c)))
+        return {f: getattr(c, f) for f, _ in tlb_server_counters._fields_}
+
+    def close(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            lib.tlb_server_destroy(h)
+            self.h = None
+
+    def __del__(self):
+        self.close()

@@ -305,3 +305,63 @@ def bandwidth_case(nx, ny):
     fl = fluid(sigma=(5e-3,) * 3, M0=5e-4, rho=(10, 10, 1))
     return _problem("sweep_%dx%d" % (nx, ny), nx, ny, fl, (1, 1), mask, [material(90, 90)],
                     z, z, steps=500)
+
+
+def serving_request(rng: Rng, n: int, kind: int, precision_steps=(1000, 20000)):
+    """One serving request: a single (kind 0), binary (1) or compound (2)
+    drop on the bottom wall of an n x n channel; contact angles ~ U[30, 150]
+    deg, surface tensions ~ U[5e-4, 2e-3] (admissible draws), steps ~
+    U{lo..hi}."""
+    D = 4.0
+    while True:
+        th13, th23 = rng.uniform(30.0, 150.0), rng.uniform(30.0, 150.0)
+        sig = (rng.uniform(5e-4, 2e-3), rng.uniform(5e-4, 2e-3), rng.uniform(5e-4, 2e-3))
+        if admissible(*sig, theta13=th13, theta23=th23):
+            break
+    mask = channel_mask(n, n)
+    mats = [material(th13, th23), material(90.0, 90.0)]
+    R = n / 8.0
+    if kind == 0:
+        c1 = tanh_drop(n, n, n / 2.0, 0.5, R, D)
+        c2 = np.zeros((n, n))
+    elif kind == 1:
+        c1 = tanh_drop(n, n, n / 2.0 - R, 0.5, R, D)
+        c2 = tanh_drop(n, n, n / 2.0 + R, 0.5, R, D)
+        c2 = np.where(c1 + c2 > 1.0, 1.0 - c1, c2)
+    else:
+        c2 = tanh_drop(n, n, n / 2.0, 0.5 + R, R / 2.0, D)
+        c1 = tanh_drop(n, n, n / 2.0, 0.5 + R, R, D) - c2
+    fl = fluid(sigma=sig, D=D, M0=0.1 * (sum(sig) / 3.0), rho=(1.0, 1.0, 1.0))
+    lo, hi = precision_steps
+    steps = lo + rng.choice(hi - lo + 1)
+    return _problem("serve_%d_k%d" % (n, kind), n, n, fl, (1, 0), mask, mats, c1, c2,
+                    steps=steps)
+
+
+def serving_stream(n_requests=1000, seed=2026, sizes=(64, 128, 256, 512, 1024),
+                   weights=(0.40, 0.30, 0.15, 0.10, 0.05), steps=(1000, 20000)):
+    """A stream of independent requests: sizes drawn with the given weights,
+    drop kind single / binary / compound with probability 1/3 each.  Returns
+    (size, kind, steps, problem-factory) tuples; arrival times are drawn by
+    the caller (Poisson at a chosen rate)."""
+    rng = Rng(seed)
+    cum = np.cumsum(weights) / np.sum(weights)
+    out = []
+    for _ in range(n_requests):
+        u = rng.uniform()
+        n = sizes[int(np.searchsorted(cum, u, side="right"))] if u < cum[-1] else sizes[-1]
+        kind = rng.choice(3)
+        sub = Rng(rng.next_u64())
+        out.append((n, kind, sub))
+    return [(n, kind, (lambda n=n, kind=kind, sub=sub: serving_request(Rng(sub.s), n, kind, steps)))
+            for n, kind, sub in out]
+
+
+def poisson_arrivals(n, rate, seed=7):
+    """n arrival times (seconds) of a Poisson process with the given rate."""
+    rng = Rng(seed)
+    t, out = 0.0, []
+    for _ in range(n):
+        t += -math.log(1.0 - rng.uniform()) / rate
+        out.append(t)
+    return out
