@@ -19,6 +19,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -89,6 +91,106 @@ def time_precision(tlb, torch, problem, precision, steps, warmup):
     return dt, kms, m
 
 
+def batching_leg(tlb, torch, precision="fp32", n_lattices=256, size=64, steps=200):
+    """Many small lattices (the serving stream's most common size) advanced
+    one at a time versus together in one batched, graph-replayed launch per
+    step."""
+    from paper_1710_09534_amd import workloads as W
+    rng = W.Rng(99)
+    probs = [W.serving_request(W.Rng(rng.next_u64()), size, i % 3, (steps, steps))
+             for i in range(n_lattices)]
+    solvers = [tlb.from_problem(p, precision) for p in probs]
+    for s in solvers:
+        s.set_check_interval(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in solvers:
+        s.step(steps)
+    torch.cuda.synchronize()
+    t_solo = time.perf_counter() - t0
+    b = tlb.Batch(n_lattices)
+    b.set(solvers)
+    b.use_graph(50)
+    b.step(50)
+    b.sync()
+    t0 = time.perf_counter()
+    b.step(steps)
+    b.sync()
+    t_batch = time.perf_counter() - t0
+    nodes = n_lattices * size * size
+    return {"lattices": n_lattices, "size": "%dx%d" % (size, size), "precision": precision,
+            "steps": steps, "one_at_a_time_mlups": round(nodes * steps / t_solo / 1e6, 1),
+            "batched_mlups": round(nodes * steps / t_batch / 1e6, 1),
+            "speedup": round(t_solo / t_batch, 2)}
+
+
+def serving_leg(tlb, torch, precision="fp32", n_requests=120, steps=(1000, 4000),
+                arena_gb=40.0, slots=64, quantum=250):
+    """A seeded stream of independent drop solves (sizes 64^2..1024^2
+    weighted 0.40/0.30/0.15/0.10/0.05, single/binary/compound drops, random
+    angles and surface tensions) served with continuous batching under an
+    HBM arena, at Poisson loads of 0.7x and 1.2x the measured capacity; and
+    the same stream solved one request at a time by the plain FP64 path."""
+    from paper_1710_09534_amd import workloads as W
+    stream = W.serving_stream(n_requests, seed=2026, steps=steps)
+    probs = [f() for (_, _, f) in stream]
+    work = sum(p["nx"] * p["ny"] * p["steps"] for p in probs)
+
+    def run(arrivals):
+        srv = tlb.Server(int(arena_gb * (1 << 30)), max_slots=slots, precision=precision,
+                         quantum=quantum)
+        t0 = time.perf_counter()
+        ids = []
+        for p, ta in zip(probs, arrivals):
+            now = time.perf_counter() - t0
+            if ta > now:
+                time.sleep(ta - now)
+            ids.append(srv.submit(p, p["steps"], fields=0))
+        for i in ids:
+            srv.wait(i, 600.0)
+        makespan = time.perf_counter() - t0
+        lat = np.array([srv.latency(i) for i in ids])
+        st = srv.stats()
+        srv.close()
+        return makespan, lat, st
+
+    # capacity: everything submitted at once
+    makespan, lat, st = run([0.0] * len(probs))
+    cap = len(probs) / makespan
+    out = {"requests": len(probs), "precision": precision, "steps_range": list(steps),
+           "arena_gb": arena_gb, "slots": slots, "quantum": quantum,
+           "capacity_req_per_s": round(cap, 2),
+           "closed_batch_mlups": round(work / makespan / 1e6, 1)}
+    for tag, load in (("load_0.7", 0.7), ("load_1.2", 1.2)):
+        arr = W.poisson_arrivals(len(probs), load * cap, seed=7)
+        makespan, lat, st = run(arr)
+        out[tag] = {"p50_s": round(float(np.percentile(lat, 50)), 4),
+                    "p99_s": round(float(np.percentile(lat, 99)), 4),
+                    "aggregate_mlups": round(work / makespan / 1e6, 1),
+                    "failed": int(st["failed"])}
+    # one request at a time, plain FP64, same arrivals (FIFO single server)
+    service = []
+    for p in probs:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s = tlb.from_problem(p, "fp64")
+        s.set_check_interval(0)
+        s.step(p["steps"])
+        s.mass()
+        service.append(time.perf_counter() - t0)
+        del s
+    for tag, load in (("load_0.7", 0.7), ("load_1.2", 1.2)):
+        arr = W.poisson_arrivals(len(probs), load * cap, seed=7)
+        fin, tts = 0.0, []
+        for ta, sv in zip(arr, service):
+            fin = max(fin, ta) + sv
+            tts.append(fin - ta)
+        out[tag]["sequential_fp64_p50_s"] = round(float(np.percentile(tts, 50)), 4)
+        out[tag]["sequential_fp64_p99_s"] = round(float(np.percentile(tts, 99)), 4)
+    out["sequential_fp64_mlups"] = round(work / sum(service) / 1e6, 1)
+    return out
+
+
 def cpu_baseline(problem, budget_s=12.0):
     import oracle
     o = oracle.Oracle(problem)
@@ -118,6 +220,7 @@ def main():
     ap.add_argument("--ny", type=int, default=None)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only", action="store_true", help="time the headline precision only")
+    ap.add_argument("--no-serving", action="store_true", help="skip the batching and serving legs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB, 10 times (counter scale)")
     args = ap.parse_args()
@@ -191,10 +294,15 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
-                     "kernel": "step_kernel<%s,8>" % args.precision,
+                     "kernel": "step_kernel<%d> (%s populations)" % ({"fp64": 0, "fp32": 1, "fp16dev": 2}[args.precision], args.precision),
                      "algorithmic_bytes_per_launch": alg},
         "precisions": table,
     }
+    if not (args.only or args.no_serving):
+        out["batching"] = batching_leg(tlb, torch)
+        print("# batching: %s" % out["batching"], file=sys.stderr, flush=True)
+        out["serving"] = serving_leg(tlb, torch)
+        print("# serving: %s" % out["serving"], file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(problem)
     print(json.dumps(out), flush=True)
