@@ -389,24 +389,28 @@ __device__ __forceinline__ LatView<P> lat_view(const PopBuf& b, long npad) {
     return v;
 }
 
-// population k of family f at lattice node j (element offset within a plane)
+// population k of family f at lattice node j (element offset within a plane);
+// with `on` false the load is out of range: it returns 0 and touches no memory
 template <int P>
 __device__ __forceinline__ typename Tr<P>::R bld(const LatView<P>& v,
                                                  const Consts<typename Tr<P>::R>& c, int f,
-                                                 int k, unsigned j) {
+                                                 int k, unsigned j, bool on) {
     if constexpr (P == P64) {
-        auto r = __builtin_amdgcn_raw_buffer_load_b64(v.fam[f], int(j * 8u), int(k * v.pstride), 0);
+        auto r = __builtin_amdgcn_raw_buffer_load_b64(v.fam[f], int(on ? j * 8u : kDiscard),
+                                                      int(k * v.pstride), 0);
         return __builtin_bit_cast(double, r);
     } else if constexpr (P == P32) {
-        unsigned r = __builtin_amdgcn_raw_buffer_load_b32(v.fam[f], int(j * 4u), int(k * v.pstride), 0);
+        unsigned r = __builtin_amdgcn_raw_buffer_load_b32(v.fam[f], int(on ? j * 4u : kDiscard),
+                                                          int(k * v.pstride), 0);
         return __builtin_bit_cast(float, r);
     } else {
         if (k == 0 && f < 2) {
-            unsigned r = __builtin_amdgcn_raw_buffer_load_b32(v.rest, int(j * 4u), int(f * v.rstride), 0);
+            unsigned r = __builtin_amdgcn_raw_buffer_load_b32(v.rest, int(on ? j * 4u : kDiscard),
+                                                              int(f * v.rstride), 0);
             return __builtin_bit_cast(float, r);
         }
-        unsigned short r =
-            __builtin_amdgcn_raw_buffer_load_b16(v.fam[f], int(j * 2u), int(k * v.pstride), 0);
+        unsigned short r = __builtin_amdgcn_raw_buffer_load_b16(
+            v.fam[f], int(on ? j * 2u : kDiscard), int(k * v.pstride), 0);
         return float(__builtin_bit_cast(_Float16, r)) * c.iscale[f];
     }
 }
@@ -484,19 +488,21 @@ __device__ __forceinline__ Nb32 make_nb32(const Grid& g, int x, int y) {
 // Issues the material byte and the 18 pulls of f^1, f^2 at node (gx, gy).
 // The pulls are issued whatever the material (every wrapped offset is
 // valid), so nothing waits on the byte before they go out; the values of a
-// solid node are discarded where c is formed.
+// solid node are discarded where c is formed.  A row the strip does not need
+// (`on` false) issues the same instructions out of range: no traffic, and
+// the same wait pattern as every other iteration.
 template <int P>
 __device__ __forceinline__ void pull_f(const Grid& g, const Consts<typename Tr<P>::R>& c,
                                        const LatView<P>& src, const uint8_t* __restrict__ mat,
-                                       int gx, int gy, typename Tr<P>::R* f1,
+                                       int gx, int gy, bool on, typename Tr<P>::R* f1,
                                        typename Tr<P>::R* f2, uint8_t& m) {
     const Nb32 nb = make_nb32(g, gx, gy);
     m = mat[nb.r0 + nb.x0];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
         const unsigned j = nb.up(k);
-        f1[k] = bld<P>(src, c, 0, k, j);
-        f2[k] = bld<P>(src, c, 1, k, j);
+        f1[k] = bld<P>(src, c, 0, k, j, on);
+        f2[k] = bld<P>(src, c, 1, k, j, on);
     }
 }
 
@@ -668,6 +674,7 @@ __device__ __forceinline__ void step_tile(const Grid& g, const Consts<typename T
     const int y0 = (t / g.tiles_x) * H;
     const int rows = g.ny - y0 < H ? g.ny - y0 : H;
     const int nit = (rows + 3) / 4;
+    const int ylast = y0 + rows + 1;                       // last row whose c is needed
     const int lane = threadIdx.x & (kTileX - 1);
     const int w = threadIdx.x / kTileX;
     const LatView<P> src = lat_view<P>(srcb, g.npad);
@@ -710,9 +717,10 @@ __device__ __forceinline__ void step_tile(const Grid& g, const Consts<typename T
                 sm.c2[sl] = fl ? b : R(0);
                 sm.m[sl] = nm;
             }
-            pull_f<P>(g, c, src, mat, gx, wrapc(Y + 6 + hr, g.ny), nf1, nf2, nm);
+            pull_f<P>(g, c, src, mat, gx, wrapc(Y + 6 + hr, g.ny), act && Y + 6 + hr <= ylast,
+                      nf1, nf2, nm);
         };
-        pull_f<P>(g, c, src, mat, gx, wrapc(y0 - 2 + hr, g.ny), nf1, nf2, nm);
+        pull_f<P>(g, c, src, mat, gx, wrapc(y0 - 2 + hr, g.ny), act, nf1, nf2, nm);
         halo_a(-1);
         __syncthreads();
         phase_b(-1);
@@ -762,28 +770,30 @@ __device__ __forceinline__ void step_tile(const Grid& g, const Consts<typename T
                 sm.stash[it & 1][w - 2][9 + k][lane] = cf2[k];
             }
         }
-        // issued on every path, at in-range offsets, before the next row's
-        // pulls so that waiting for them leaves those in flight
+        // issued on every path before the next row's pulls so that waiting
+        // for them leaves those in flight; rows outside the strip load out of
+        // range (no traffic)
         yo = Y + ((w + 2) & 3);
         nb = make_nb32(g, gxl, wrapc(yo, g.ny));
         idx = nb.r0 + nb.x0;
+        const bool gon = yo >= y0 && yo < y0 + rows;
 #pragma unroll
-        for (int k = 0; k < 9; ++k) gg[k] = bld<P>(src, c, 2, k, nb.up(k));
+        for (int k = 0; k < 9; ++k) gg[k] = bld<P>(src, c, 2, k, nb.up(k), gon);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             if constexpr (P == P64)
                 ho[q] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
-                                                       hist, int(idx * 8u), int(q * hstride), 0));
+                    hist, int(gon ? idx * 8u : kDiscard), int(q * hstride), 0));
             else
                 ho[q] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
-                                                      hist, int(idx * 4u), int(q * hstride), 0));
+                    hist, int(gon ? idx * 4u : kDiscard), int(q * hstride), 0));
         }
         __builtin_amdgcn_sched_barrier(0);
-        pull_f<P>(g, c, src, mat, gxl, wrapc(Y + 6 + w, g.ny), nf1, nf2, nm);
+        pull_f<P>(g, c, src, mat, gxl, wrapc(Y + 6 + w, g.ny), Y + 6 + w <= ylast, nf1, nf2, nm);
         __builtin_amdgcn_sched_barrier(0);
     };
 
-    pull_f<P>(g, c, src, mat, gxl, wrapc(y0 - 2 + w, g.ny), nf1, nf2, nm);
+    pull_f<P>(g, c, src, mat, gxl, wrapc(y0 - 2 + w, g.ny), true, nf1, nf2, nm);
     phase_a(-1);
     __syncthreads();
     phase_b(-1);
@@ -819,8 +829,8 @@ __device__ __forceinline__ void step_tile(const Grid& g, const Consts<typename T
             node_update<P>(g, c, s, sm.mt, nb, idx, live, mask, cf1, cf2, gg, ho, dst, hist,
                            hstride);
         }
-        // phase A of the next iteration (after the last one it only issues
-        // harmless in-range loads)
+        // phase A of the next iteration (after the last one its loads are
+        // all out of range)
         phase_a(it + 1);
     }
 }
