@@ -47,7 +47,7 @@ class _Fluid(C.Structure):
 
 class _Material(C.Structure):
     _fields_ = [("theta13_deg", C.c_double), ("theta23_deg", C.c_double),
-                ("wall_u", C.c_double * 2)]
+                ("wall_u", C.c_double * 2), ("kind", C.c_int)]
 
 
 class _Derived(C.Structure):
@@ -176,7 +176,7 @@ def sources(tau1, tau2, taug, d1, d2, u, grad_rho, force, fa):
 class Oracle:
     """Whole-lattice FP64 oracle.  ``problem`` is a dict with keys nx, ny,
     fluid, periodic (px, py), material (uint8 [ny, nx]), mats (list of dicts
-    with theta13, theta23, wall_u)."""
+    with theta13, theta23, wall_u and kind: 0 wall, 1 velocity boundary)."""
 
     def __init__(self, problem: dict, threads: int | None = None):
         self._lib = _load()
@@ -192,6 +192,7 @@ class Oracle:
             arr[i].theta23_deg = m["theta23"]
             wu = m.get("wall_u", (0.0, 0.0))
             arr[i].wall_u[0], arr[i].wall_u[1] = wu[0], wu[1]
+            arr[i].kind = int(m.get("kind", 0))
         self._fl = _fluid(problem["fluid"])
         h = C.c_void_p()
         px, py = problem.get("periodic", (1, 1))

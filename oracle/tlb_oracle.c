@@ -17,8 +17,14 @@
  *   S9  Euler time derivative of c_i u (Eq. 19)
  *   S10 equilibria (Eqs. 2, 4) and source terms (Eq. 11)
  *   S11 BGK collision (Eq. 45)
+ *   S11b post-collision populations of velocity boundary nodes by the
+ *       non-equilibrium extrapolation scheme (Eqs. 51-53)
  *   S12 streaming with half-way bounce-back (Eq. 44) and, for a moving wall,
  *       the momentum correction of the bounced populations.
+ * A velocity boundary node x_u shows, to every stencil and to its own
+ * equilibria, the macroscopic values of the fluid node x_f directly inside
+ * it (the interpolation chi(x_u) = chi(x_f) stated with Eq. 53); only the
+ * velocity is the prescribed one.
  * Built with -O2 -ffp-contract=off; OpenMP only splits rows of a loop, so
  * results do not depend on the thread count.
  */
@@ -188,6 +194,7 @@ void orc_sources(double tau1, double tau2, double taug,
 typedef struct {
     double cos12, cos13, cos23;
     double uw[2];
+    int kind;     /* ORC_WALL or ORC_VELOCITY */
 } mat_t;
 
 struct orc_sim {
@@ -198,6 +205,10 @@ struct orc_sim {
     uint8_t* mat;
     int nmat;
     mat_t* mats;
+    /* per node: 0 fluid, 1 wall, 2 velocity boundary; inner[i] is the fluid
+     * node directly inside velocity boundary node i (else -1) */
+    uint8_t* cls;
+    long* inner;
     int inited;
     /* state: populations f(x,t) after streaming, and history at t-1 */
     double *f1[9], *f2[9], *g[9];
@@ -249,6 +260,8 @@ void orc_destroy(orc_sim* s) {
     }
     free(s->mat);
     free(s->mats);
+    free(s->cls);
+    free(s->inner);
     free(s);
 }
 
@@ -286,7 +299,16 @@ int orc_create(int nx, int ny, const orc_fluid* fl, int periodic_x, int periodic
     s->mats = (mat_t*)calloc((size_t)(n_mats > 0 ? n_mats : 1), sizeof(mat_t));
     const double d2r = acos(-1.0) / 180.0;
     for (int m = 0; m < n_mats; ++m) {
-        double c12;
+        double c12 = 0.0;
+        if (mats[m].kind != ORC_WALL && mats[m].kind != ORC_VELOCITY) {
+            set_err("unknown material kind");
+            orc_destroy(s);
+            return -1;
+        }
+        s->mats[m].kind = mats[m].kind;
+        s->mats[m].uw[0] = mats[m].wall_u[0];
+        s->mats[m].uw[1] = mats[m].wall_u[1];
+        if (mats[m].kind == ORC_VELOCITY) continue;
         if (orc_cos12(fl, mats[m].theta13_deg, mats[m].theta23_deg, &c12) != 0) {
             set_err("contact angles give |cos theta12| > 1 (Eq. 39)");
             orc_destroy(s);
@@ -295,8 +317,6 @@ int orc_create(int nx, int ny, const orc_fluid* fl, int periodic_x, int periodic
         s->mats[m].cos12 = c12;
         s->mats[m].cos13 = cos(mats[m].theta13_deg * d2r);
         s->mats[m].cos23 = cos(mats[m].theta23_deg * d2r);
-        s->mats[m].uw[0] = mats[m].wall_u[0];
-        s->mats[m].uw[1] = mats[m].wall_u[1];
     }
     s->mat = (uint8_t*)malloc((size_t)s->n);
     memcpy(s->mat, material, (size_t)s->n);
@@ -307,6 +327,30 @@ int orc_create(int nx, int ny, const orc_fluid* fl, int periodic_x, int periodic
             return -1;
         }
     }
+    s->cls = (uint8_t*)malloc((size_t)s->n);
+    s->inner = (long*)malloc((size_t)s->n * sizeof(long));
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            long i = (long)y * nx + x;
+            s->inner[i] = -1;
+            if (!s->mat[i]) { s->cls[i] = 0; continue; }
+            if (s->mats[s->mat[i] - 1].kind == ORC_WALL) { s->cls[i] = 1; continue; }
+            /* velocity boundary node: bottom or top row of a y-bounded lattice */
+            s->cls[i] = 2;
+            if (s->py || (y != 0 && y != ny - 1)) {
+                set_err("velocity boundary nodes must lie in the bottom or top row of a "
+                        "lattice that is not periodic in y");
+                orc_destroy(s);
+                return -1;
+            }
+            s->inner[i] = (long)(y == 0 ? 1 : ny - 2) * nx + x;
+        }
+    for (long i = 0; i < s->n; ++i)
+        if (s->cls[i] == 2 && s->mat[s->inner[i]]) {
+            set_err("the node inside a velocity boundary node must be fluid");
+            orc_destroy(s);
+            return -1;
+        }
     /* a fluid node may not touch the edge of a non-periodic direction */
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
@@ -350,7 +394,9 @@ static void lap_c_wetting(orc_sim* s, int comp, const double* ci, double* lap) {
             for (int k = 1; k < 9; ++k) {
                 long j = nbr(s, x, y, k);
                 double chat;
-                if (s->mat[j]) {
+                if (s->cls[j] == 2) {
+                    chat = ci[s->inner[j]];          /* Eq. 53: chi(x_u) = chi(x_f) */
+                } else if (s->cls[j] == 1) {
                     const mat_t* m = &s->mats[s->mat[j] - 1];
                     double gh[3];
                     orc_wetting_ghost(s->fl.D, m->cos12, m->cos13, m->cos23,
@@ -365,6 +411,15 @@ static void lap_c_wetting(orc_sim* s, int comp, const double* ci, double* lap) {
         }
 }
 
+/* value of chi seen across the link to neighbour j of fluid node i: a wall
+ * neighbour takes chi(i) (symmetric ghost, Eq. 43), a velocity boundary
+ * neighbour the value at the fluid node inside it (Eq. 53) */
+static double across(const orc_sim* s, const double* chi, long i, long j) {
+    if (s->cls[j] == 1) return chi[i];
+    if (s->cls[j] == 2) return chi[s->inner[j]];
+    return chi[j];
+}
+
 /* Eq. 20a with the symmetric ghost of Eq. 43 (solid neighbour takes chi(x_f)) */
 int orc_grad_field(orc_sim* s, const double* chi, double* gx, double* gy) {
     const int nx = s->nx, ny = s->ny;
@@ -376,7 +431,7 @@ int orc_grad_field(orc_sim* s, const double* chi, double* gx, double* gy) {
             double ax = 0.0, ay = 0.0;
             for (int k = 1; k < 9; ++k) {
                 long j = nbr(s, x, y, k);
-                double v = s->mat[j] ? chi[i] : chi[j];
+                double v = across(s, chi, i, j);
                 ax += W[k] * EX[k] * v / CS2;
                 ay += W[k] * EY[k] * v / CS2;
             }
@@ -397,7 +452,7 @@ int orc_lap_field(orc_sim* s, const double* chi, double* lap) {
             double acc = 0.0;
             for (int k = 1; k < 9; ++k) {
                 long j = nbr(s, x, y, k);
-                double v = s->mat[j] ? chi[i] : chi[j];
+                double v = across(s, chi, i, j);
                 acc += 2.0 * W[k] * (v - chi[i]) / CS2;
             }
             lap[i] = acc;
@@ -586,6 +641,38 @@ int orc_step(orc_sim* s, int nsteps) {
                 s->gp[k][i] = s->g[k][i] - (s->g[k][i] - s->ge[k][i]) / s->taug[i] + s->Gk[k][i];
             }
         }
+        /* S11b: velocity boundary nodes (Eqs. 51-53).  The populations of x_u
+         * are its equilibrium plus the non-equilibrium part of x_f (Eq. 51,
+         * 52); the equilibrium uses x_f's c_i, mu_i, p, rho and the prescribed
+         * u (Eq. 53).  x_u then collides like any node (Eq. 45), with source
+         * terms (Eq. 11) formed the same way: every macroscopic quantity but u
+         * from x_f, u = u_w (so d(c_i u)/dt = u_w (c_i - c_i^old) at x_f and
+         * F_a = u_w times x_f's interfacial coefficient). */
+#pragma omp parallel for schedule(static)
+        for (long j = 0; j < s->n; ++j) {
+            if (s->cls[j] != 2) continue;
+            const long i = s->inner[j];
+            const mat_t* m = &s->mats[s->mat[j] - 1];
+            const double uwx = m->uw[0], uwy = m->uw[1];
+            double fe1[9], fe2[9], ge[9], F1[9], F2[9], G[9];
+            orc_equilibria(s->c1[i], s->c2[i], s->d.eta[0], s->d.eta[1], s->mu1[i], s->mu2[i],
+                           s->rho[i], s->p[i], uwx, uwy, fe1, fe2, ge);
+            const double dc1 = s->c1[i] - s->c1o[i], dc2 = s->c2[i] - s->c2o[i];
+            const double a = (s->fl.rho[0] - s->fl.rho[2]) * s->d.M[0] * s->lmu1[i]
+                           + (s->fl.rho[1] - s->fl.rho[2]) * s->d.M[1] * s->lmu2[i];
+            orc_sources(t1, t2, s->taug[i], uwx * dc1, uwy * dc1, uwx * dc2, uwy * dc2,
+                        uwx, uwy, s->grx[i], s->gry[i],
+                        s->fsx[i] + s->gbx[i], s->fsy[i] + s->gby[i], uwx * a, uwy * a,
+                        F1, F2, G);
+            for (int k = 0; k < 9; ++k) {
+                const double f1u = fe1[k] + (s->f1[k][i] - s->fe1[k][i]);   /* Eq. 51 */
+                const double f2u = fe2[k] + (s->f2[k][i] - s->fe2[k][i]);
+                const double gu = ge[k] + (s->g[k][i] - s->ge[k][i]);
+                s->fp1[k][j] = f1u - (f1u - fe1[k]) / t1 + F1[k];           /* Eq. 45 */
+                s->fp2[k][j] = f2u - (f2u - fe2[k]) / t2 + F2[k];
+                s->gp[k][j] = gu - (gu - ge[k]) / s->taug[i] + G[k];
+            }
+        }
         /* S9 (history) now that the old values are consumed */
 #pragma omp parallel for schedule(static)
         for (long i = 0; i < s->n; ++i) {
@@ -595,10 +682,11 @@ int orc_step(orc_sim* s, int nsteps) {
             s->uxo[i] = s->ux[i];
             s->uyo[i] = s->uy[i];
         }
-        /* S12: pull streaming; a link whose upstream node is solid takes the
-         * node's own post-collision population of the opposite direction
-         * (Eq. 44), plus the moving-wall momentum term 2 w_k a e_k.u_w / c_s^2
-         * with a = c_i for f^i and a = rho for g. */
+        /* S12: pull streaming from fluid and velocity boundary nodes; a link
+         * whose upstream node is a wall takes the node's own post-collision
+         * population of the opposite direction (Eq. 44), plus the moving-wall
+         * momentum term 2 w_k a e_k.u_w / c_s^2 with a = c_i for f^i and
+         * a = rho for g. */
 #pragma omp parallel for schedule(static)
         for (int y = 0; y < ny; ++y)
             for (int x = 0; x < nx; ++x) {
@@ -606,7 +694,7 @@ int orc_step(orc_sim* s, int nsteps) {
                 if (s->mat[i]) continue;
                 for (int k = 0; k < 9; ++k) {
                     long j = nbr(s, x, y, OPP[k]); /* x - e_k */
-                    if (!s->mat[j]) {
+                    if (s->cls[j] != 1) {
                         s->f1[k][i] = s->fp1[k][j];
                         s->f2[k][i] = s->fp2[k][j];
                         s->g[k][i] = s->gp[k][j];

@@ -16,7 +16,8 @@
  *
  * Conventions: lattice units (dx = dt = 1); fields are row-major with x
  * fastest, index = y*nx + x, y = 0 is the bottom row.  material[idx] == 0
- * is a fluid node, m >= 1 a solid node of material mats[m-1].
+ * is a fluid node, m >= 1 a boundary node of material mats[m-1]: a solid
+ * wall, or a velocity boundary node (Sec. III, Eqs. 51-53).
  */
 #ifndef TLB_ORACLE_H
 #define TLB_ORACLE_H
@@ -36,9 +37,20 @@ typedef struct {
     double gravity[2];                /* body force G = rho * gravity */
 } orc_fluid;
 
+/* material kinds */
+enum { ORC_WALL = 0, ORC_VELOCITY = 1 };
+
 typedef struct {
-    double theta13_deg, theta23_deg;  /* theta12 follows from Eq. 39 */
-    double wall_u[2];                 /* tangential wall velocity (moving wall) */
+    double theta13_deg, theta23_deg;  /* theta12 follows from Eq. 39 (walls only) */
+    double wall_u[2];                 /* wall velocity (ORC_WALL), or the prescribed
+                                         boundary velocity (ORC_VELOCITY) */
+    int kind;                         /* ORC_WALL: solid wall with the wetting scheme
+                                         (Eqs. 42-44); ORC_VELOCITY: velocity boundary
+                                         node of the non-equilibrium extrapolation
+                                         scheme (Eqs. 51-53), allowed only in the
+                                         bottom or top row of a lattice that is not
+                                         periodic in y, with a fluid node directly
+                                         inside it */
 } orc_material;
 
 /* derived parameters, see orc_params() */

@@ -100,9 +100,21 @@ def fluid(sigma=(1e-3, 1e-3, 1e-3), D=4.0, M0=1e-4, tau=(0.8, 0.8), rho=(1.0, 1.
             "gravity": [float(g) for g in gravity]}
 
 
+WALL, VELOCITY = 0, 1     # material kinds
+
+
 def material(theta13, theta23, wall_u=(0.0, 0.0)) -> dict:
+    """A solid wall with contact angles theta13, theta23 (degrees) moving
+    tangentially at wall_u."""
     return {"theta13": float(theta13), "theta23": float(theta23),
-            "wall_u": [float(wall_u[0]), float(wall_u[1])]}
+            "wall_u": [float(wall_u[0]), float(wall_u[1])], "kind": WALL}
+
+
+def velocity_boundary(u) -> dict:
+    """A row of velocity boundary nodes with prescribed velocity u (the
+    non-equilibrium extrapolation boundary of Sec. III.D)."""
+    return {"theta13": 90.0, "theta23": 90.0, "wall_u": [float(u[0]), float(u[1])],
+            "kind": VELOCITY}
 
 
 def admissible(sigma12, sigma13, sigma23, theta13=None, theta23=None) -> bool:
@@ -212,6 +224,30 @@ def compound_shear(seed=0, nx=512, ny=256, U=0.01, R_core=20.0, R_shell=40.0, st
                nu=(nu, nu, nu))
     return _problem("compound_shear_%dx%d_s%d" % (nx, ny, seed), nx, ny, fl, (1, 0), mask,
                     mats, shell, core, steps=steps, theta13=th13, Ca=ca, U=U)
+
+
+def nee_shear(nx=400, ny=150, U0=0.1, R_core=25.5, R_shell=60.0, offset=7.5,
+              sigma=0.01, M0=1e-3, steps=30000):
+    """Compound drop sheared by a velocity boundary (Sec. III.D): periodic in x,
+    a wetting wall in row 0 (theta12 = 30, theta13 = 68.53, theta23 = 120),
+    velocity boundary nodes moving at (U0, 0) in the top row.  Phase-2 drop
+    of radius R_shell with a phase-1 core of radius R_core, both centred on
+    the wall surface y = 1/2, the core shifted by `offset` along x.
+    sigma = 0.01 for every pair, tau = 0.8, M0 = 1e-3, unit densities."""
+    D = 4.0
+    xs = 0.5 * nx - 0.5 * offset
+    core = tanh_drop(nx, ny, xs + offset, 0.5, R_core, D)
+    shell = tanh_drop(nx, ny, xs, 0.5, R_shell, D) - core
+    mask = np.zeros((ny, nx), dtype=np.uint8)
+    mask[0, :] = 1
+    mask[ny - 1, :] = 2
+    core[mask != 0] = 0.0
+    shell[mask != 0] = 0.0
+    mats = [material(68.53, 120.0), velocity_boundary((U0, 0.0))]
+    fl = fluid(sigma=(sigma, sigma, sigma), D=D, M0=M0, tau=(0.8, 0.8), rho=(1, 1, 1),
+               nu=(0.1, 0.1, 0.1))
+    return _problem("nee_shear_%dx%d_U%g" % (nx, ny, U0), nx, ny, fl, (1, 0), mask, mats,
+                    core, np.clip(shell, 0.0, None), steps=steps, U0=U0)
 
 
 def cylinder_impact(We=10.0, theta=90.0, nx=1024, ny=2048, R_cyl=128.0, R_shell=96.0,
