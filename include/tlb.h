@@ -70,11 +70,29 @@ typedef struct {
     double gravity[2];                /* body force G = rho * gravity (Sec. III.A) */
 } tlb_fluid;
 
-/* A solid material: its wettability and its tangential wall velocity. */
+/* Material kinds. */
+enum {
+    TLB_WALL = 0,     /* solid wall: wetting ghosts (Eq. 42), symmetric ghosts (Eq. 43),
+                         half-way bounce-back (Eq. 44) */
+    TLB_VELOCITY = 1  /* velocity boundary node of the non-equilibrium extrapolation
+                         scheme (Sec. III.D, Eqs. 51-53) */
+};
+
+/* A boundary material.  For TLB_WALL: its wettability and its tangential wall
+ * velocity.  For TLB_VELOCITY: wall_u is the prescribed velocity u_w of the
+ * boundary nodes, the angles are ignored.  A velocity boundary node x_u
+ * takes, for every macroscopic quantity but u, the value at the fluid node
+ * x_f directly inside it (chi(x_u) = chi(x_f), as stated with Eq. 53): its
+ * populations are its equilibrium (Eq. 53) plus the non-equilibrium part of
+ * x_f (Eqs. 51-52), collided like any node (Eq. 45) with the source terms of
+ * Eq. 11 formed from x_f's quantities and u = u_w; stencils at fluid nodes
+ * see x_u with x_f's values. */
 typedef struct {
     double theta13_deg, theta23_deg; /* static contact angles, Eq. 38; theta12 from Eq. 39 */
     double wall_u[2];                /* wall velocity (bounce-back with the moving-wall
-                                        momentum term; 0 = the paper's resting wall) */
+                                        momentum term; 0 = the paper's resting wall), or
+                                        the boundary velocity of a TLB_VELOCITY material */
+    int kind;                        /* TLB_WALL or TLB_VELOCITY */
 } tlb_material;
 
 /* field bits of tlb_read_fields; fields are written in this bit order */
@@ -102,11 +120,15 @@ tlb_status tlb_create(int nx, int ny, tlb_precision p, const tlb_fluid* fl,
                       void* dev_workspace, size_t ws_bytes, void* hip_stream,
                       tlb_ctx** out);
 
-/* Solid geometry and wettability.  material: host uint8 [ny*nx]; mats[m-1]
- * for each material id m in 1..n_mats (n_mats <= 15).  theta12 of each
+/* Boundary geometry and wettability.  material: host uint8 [ny*nx]; mats[m-1]
+ * for each material id m in 1..n_mats (n_mats <= 15).  theta12 of each wall
  * material is derived from Eq. 39 (sigma12 cos12 = sigma13 cos13 - sigma23
- * cos23) and written to theta12_out[n_mats] in degrees when non-NULL;
- * |cos theta12| > 1 is TLB_EPARAM.  Must precede tlb_init_fields. */
+ * cos23) and written to theta12_out[n_mats] in degrees when non-NULL (NaN for
+ * a velocity material); |cos theta12| > 1 is TLB_EPARAM.  Velocity boundary
+ * nodes may only lie in row 0 or row ny-1 of a lattice with periodic_y = 0,
+ * and the node directly inside each (row 1 or ny-2) must be fluid; an
+ * unknown kind or a misplaced velocity node is TLB_EINVAL.  Must precede
+ * tlb_init_fields. */
 tlb_status tlb_set_geometry(tlb_ctx* ctx, int periodic_x, int periodic_y,
                             const uint8_t* material, const tlb_material* mats,
                             int n_mats, double* theta12_out);

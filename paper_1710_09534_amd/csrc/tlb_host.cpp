@@ -138,6 +138,7 @@ void fill_consts(Consts<R>& k, const tlb_ctx* c) {
         k.scale[i] = 1.0f;
         k.iscale[i] = 1.0f;
     }
+    k.nee = 0u;
 }
 
 void set_grid(tlb_ctx* c, int rows) {
@@ -293,24 +294,47 @@ tlb_status tlb_set_geometry(tlb_ctx* c, int periodic_x, int periodic_y, const ui
     if (!periodic_y)
         for (int x = 0; x < nx; ++x)
             if (!material[x] || !material[long(ny - 1) * nx + x])
-                return fail(c, TLB_EINVAL, "non-periodic y needs solid rows 0 and ny-1");
+                return fail(c, TLB_EINVAL, "non-periodic y needs boundary rows 0 and ny-1");
+    unsigned nee = 0;
+    for (int m = 0; m < n_mats; ++m) {
+        if (mats[m].kind != TLB_WALL && mats[m].kind != TLB_VELOCITY)
+            return fail(c, TLB_EINVAL, "unknown material kind");
+        if (mats[m].kind == TLB_VELOCITY) nee |= 1u << (m + 1);
+    }
+    // velocity boundary nodes: rows 0 / ny-1 of a y-bounded lattice, with a
+    // fluid node directly inside (the x_f of Eqs. 51-53)
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            const int m = material[long(y) * nx + x];
+            if (!((nee >> m) & 1u)) continue;
+            if (periodic_y || (y != 0 && y != ny - 1))
+                return fail(c, TLB_EINVAL, "velocity boundary nodes must lie in row 0 or "
+                                           "ny-1 of a lattice not periodic in y");
+            const int yi = y == 0 ? 1 : ny - 2;
+            if (material[long(yi) * nx + x])
+                return fail(c, TLB_EINVAL, "the node inside a velocity boundary node must be fluid");
+        }
     double tab[kMatStride * (kMaxMaterials + 1)] = {};
     std::vector<double> th12(size_t(n_mats > 0 ? n_mats : 1));
     const double d2r = std::acos(-1.0) / 180.0;
     for (int m = 0; m < n_mats; ++m) {
+        if (!std::isfinite(mats[m].wall_u[0]) || !std::isfinite(mats[m].wall_u[1]))
+            return fail(c, TLB_EPARAM, "wall velocity must be finite");
+        double* t = &tab[kMatStride * (m + 1)];
+        t[3] = mats[m].wall_u[0];
+        t[4] = mats[m].wall_u[1];
+        if (mats[m].kind == TLB_VELOCITY) {
+            th12[size_t(m)] = std::nan("");
+            continue;
+        }
         double c13 = std::cos(mats[m].theta13_deg * d2r);
         double c23 = std::cos(mats[m].theta23_deg * d2r);
         double c12 = (c->fl.sigma13 * c13 - c->fl.sigma23 * c23) / c->fl.sigma12;  // Eq. 39
         if (!(std::fabs(c12) <= 1.0))
             return fail(c, TLB_EPARAM, "contact angles give |cos theta12| > 1 (Eq. 39)");
-        if (!std::isfinite(mats[m].wall_u[0]) || !std::isfinite(mats[m].wall_u[1]))
-            return fail(c, TLB_EPARAM, "wall velocity must be finite");
-        double* t = &tab[kMatStride * (m + 1)];
         t[0] = c12;
         t[1] = c13;
         t[2] = c23;
-        t[3] = mats[m].wall_u[0];
-        t[4] = mats[m].wall_u[1];
         th12[size_t(m)] = std::acos(c12) / d2r;
     }
     // upload the padded material plane
@@ -323,6 +347,8 @@ tlb_status tlb_set_geometry(tlb_ctx* c, int periodic_x, int periodic_y, const ui
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return dev_fail(c, e, "set_geometry upload");
     std::memcpy(c->mtab_host, tab, sizeof(tab));
+    c->c64.nee = nee;
+    c->c32.nee = nee;
     c->n_mats = n_mats;
     c->px = periodic_x != 0;
     c->py = periodic_y != 0;
@@ -356,6 +382,9 @@ tlb_status tlb_init_fields(tlb_ctx* c, const double* c1, const double* c2, const
             double u2 = (ux ? ux[i] * ux[i] : 0.0) + (uy ? uy[i] * uy[i] : 0.0);
             umax = std::fmax(umax, std::sqrt(u2));
         }
+        for (int m = 1; m <= c->n_mats; ++m)   // walls and velocity boundaries drive the flow
+            umax = std::fmax(umax, std::hypot(c->mtab_host[kMatStride * m + 3],
+                                              c->mtab_host[kMatStride * m + 4]));
         const double m = std::fmax(umax, 0.02);
         const double rmax = std::fmax(c->fl.rho[0], std::fmax(c->fl.rho[1], c->fl.rho[2]));
         const double fmaxv[3] = {m + 1e-2, m + 1e-2, rmax * m + 1e-2};
@@ -386,8 +415,8 @@ tlb_status tlb_init_fields(tlb_ctx* c, const double* c1, const double* c2, const
 
 static tlb_status step_impl(tlb_ctx* c, int64_t nsteps, bool checks) {
     for (int64_t s = 0; s < nsteps; ++s) {
-        hipError_t e = launch_step(c->prec, c->ws + c->L.off_desc, 1, ntiles(c), c->cur,
-                                   c->stream);
+        hipError_t e = launch_step(c->prec, c->c64.nee != 0u, c->ws + c->L.off_desc, 1,
+                                   ntiles(c), c->cur, c->stream);
         if (e != hipSuccess) return dev_fail(c, e, "step kernel");
         c->cur = 1 - c->cur;
         ++c->steps;
@@ -575,6 +604,7 @@ struct tlb_batch {
     std::vector<int> base_cur;         // each member's cur when the table was written
     std::vector<unsigned char> host;   // staged table
     int total_tiles = 0;
+    bool vel = false;                  // some member has velocity boundary nodes
     int parity = 0;                    // parity of the next step relative to the table
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -624,9 +654,11 @@ tlb_status tlb_batch_set(tlb_batch* b, tlb_ctx* const* ctxs, int n) {
     if (!b || (n > 0 && !ctxs) || n < 0) return bfail(b, TLB_EINVAL, "null batch or contexts");
     if (n > b->cap) return bfail(b, TLB_EINVAL, "more lattices than the batch capacity");
     int prec = -1, tiles = 0;
+    bool vel = false;
     for (int i = 0; i < n; ++i) {
         tlb_ctx* c = ctxs[i];
         if (!c) return bfail(b, TLB_EINVAL, "null context in batch");
+        vel = vel || c->c64.nee != 0u;
         if (!c->inited) return bfail(b, TLB_ESTATE, "every context must be initialised");
         if (c->diverged) return bfail(b, TLB_EDIVERGED, "a context has diverged");
         if (prec >= 0 && c->prec != prec) return bfail(b, TLB_EINVAL, "mixed precisions in batch");
@@ -657,6 +689,7 @@ tlb_status tlb_batch_set(tlb_batch* b, tlb_ctx* const* ctxs, int n) {
     for (int i = 0; i < n; ++i) b->base_cur[size_t(i)] = ctxs[i]->cur;
     b->prec = prec;
     b->total_tiles = tiles;
+    b->vel = vel;
     b->parity = 0;
     return TLB_OK;
 }
@@ -670,7 +703,8 @@ tlb_status tlb_batch_use_graph(tlb_batch* b, int steps) {
     if (e != hipSuccess) return bfail(b, TLB_EDEVICE, std::string("begin capture: ") + hipGetErrorString(e));
     hipError_t le = hipSuccess;
     for (int s = 0; s < steps && le == hipSuccess; ++s)
-        le = launch_step(b->prec, b->dev, int(b->ctxs.size()), b->total_tiles, s & 1, b->stream);
+        le = launch_step(b->prec, b->vel, b->dev, int(b->ctxs.size()), b->total_tiles, s & 1,
+                         b->stream);
     e = hipStreamEndCapture(b->stream, &b->graph);
     if (le != hipSuccess || e != hipSuccess) {
         drop_graph(b);
@@ -704,7 +738,7 @@ tlb_status tlb_batch_step(tlb_batch* b, int64_t nsteps) {
             done += b->graph_steps;
             continue;   // even step count: parity unchanged
         }
-        e = launch_step(b->prec, b->dev, nd, b->total_tiles, b->parity, b->stream);
+        e = launch_step(b->prec, b->vel, b->dev, nd, b->total_tiles, b->parity, b->stream);
         if (e != hipSuccess) return bfail(b, TLB_EDEVICE, std::string("batch step: ") + hipGetErrorString(e));
         b->parity ^= 1;
         ++done;

@@ -39,11 +39,14 @@ struct Consts {
     R k12D, k34D, k4D;           // 12/D, 3D/4, 4/D
     R gx, gy;                    // gravity
     float scale[3], iscale[3];   // P16 storage scales per family
+    unsigned nee;                // bit m set: material m is a velocity boundary
+                                 // (non-equilibrium extrapolation, Eqs. 51-53)
 };
 
 // Per-material table (device memory, FP64): for material id m in 0..15 the
 // five values cos(theta12), cos(theta13), cos(theta23), u_wall_x, u_wall_y at
-// mtab[5*m .. 5*m+4]; id 0 (fluid) is all zero.
+// mtab[5*m .. 5*m+4]; id 0 (fluid) is all zero.  For a velocity boundary
+// material the cosines are 0 and (u_wall_x, u_wall_y) is the boundary velocity.
 constexpr int kMatStride = 5;
 
 struct Grid {
@@ -71,9 +74,10 @@ constexpr size_t kDescBytes = 512;  // >= sizeof(LatDesc), a multiple of 256
 
 // host-side launchers (tlb_kernels.hip)
 // Step kernel over a device table of descriptors (LatDesc<double,double> for
-// P64, LatDesc<float,float> otherwise); total_tiles = sum of strip counts.
-hipError_t launch_step(int prec, const void* descs, int ndesc, int total_tiles, int parity,
-                       hipStream_t s);
+// P64, LatDesc<float,float> otherwise); total_tiles = sum of strip counts;
+// vel: some lattice of the table has velocity boundary nodes.
+hipError_t launch_step(int prec, bool vel, const void* descs, int ndesc, int total_tiles,
+                       int parity, hipStream_t s);
 // `consts` points to a host Consts<double> (P64) or Consts<float> (P32, P16);
 // `mtab` to the device material table.
 hipError_t launch_init(int prec, const Grid& g, const void* consts, const uint8_t* mat,

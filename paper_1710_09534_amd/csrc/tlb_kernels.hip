@@ -171,7 +171,16 @@ __device__ __forceinline__ void phase_a(Smem<P, TY>& sm, const Grid& g,
 template <typename R>
 struct NodeMacro {
     R c1, c2, rho, itg, mu1, mu2, ux, uy, p, grx, gry, fx, fy, fax, fay;
+    R am;   // sum_i (rho_i - rho_3) M_i lap mu_i, so that F_a = u am (Eq. 12)
 };
+
+// Neighbour mask of a node (step kernel): bit k-1 for a wall neighbour along
+// e_k, bit 8 when the node itself is not fluid, bit 15+k for a velocity
+// boundary neighbour along e_k.
+constexpr unsigned kWallBits = 0xFFu;
+constexpr unsigned kSelfBit = 0x100u;
+constexpr unsigned kVelShift = 15u;
+constexpr unsigned kVelBits = 0xFFu << 16;
 
 // LDS neighbourhood of one node: row pointers for y-1, y, y+1 (index 0..2),
 // each already offset to the node's column.
@@ -187,25 +196,37 @@ struct Stencil {
 
 // Gradients (Eq. 20a, symmetric ghosts of Eq. 43), forces, velocity
 // (Eq. 13b), interfacial force (Eq. 12) and pressure (Eq. 13c) from the
-// pulled g and the LDS fields.
-// `mask` (bit k-1 set when the neighbour along e_k is solid) replaces the
-// LDS material bytes when MASK is true.
-template <typename R, bool MASK = false>
+// pulled g and the LDS fields.  A velocity boundary neighbour x + e_k shows
+// the value of the fluid node inside it, x + (e_kx, 0) (chi(x_u) = chi(x_f),
+// Eq. 53).  When MASK is true the neighbour mask (kWallBits, kVelBits)
+// replaces the LDS material bytes; VEL false compiles velocity boundaries out.
+template <typename R, bool MASK = false, bool VEL = true>
 __device__ __forceinline__ NodeMacro<R> node_macro(const Stencil<R>& s, const Consts<R>& c,
                                                    const R* gg, unsigned mask = 0u) {
     NodeMacro<R> o;
     const R c1 = s.c1[1][0], c2 = s.c2[1][0];
     const R mu1 = s.mu1[1][0], mu2 = s.mu2[1][0], mu3 = s.mu3;
     R g1x = R(0), g1y = R(0), g2x = R(0), g2y = R(0), lm1 = R(0), lm2 = R(0);
-    const bool any = MASK ? (mask & 255u) != 0u : true;
+    const bool any = MASK ? (mask & (VEL ? kWallBits | kVelBits : kWallBits)) != 0u : true;
 #pragma unroll
     for (int k = 1; k < 9; ++k) {
         const int r = EY[k] + 1;
-        const bool solid = any && (MASK ? ((mask >> (k - 1)) & 1u) != 0u : s.m[r][EX[k]] != 0);
-        const R v1 = solid ? c1 : s.c1[r][EX[k]];
-        const R v2 = solid ? c2 : s.c2[r][EX[k]];
-        const R w1 = solid ? mu1 : s.mu1[r][EX[k]];
-        const R w2 = solid ? mu2 : s.mu2[r][EX[k]];
+        bool solid, vel;
+        if constexpr (MASK) {
+            solid = any && ((mask >> (k - 1)) & 1u) != 0u;
+            vel = VEL && any && ((mask >> (kVelShift + k)) & 1u) != 0u;
+        } else {
+            const unsigned mn = s.m[r][EX[k]];
+            vel = ((c.nee >> mn) & 1u) != 0u;
+            solid = mn != 0u && !vel;
+        }
+        // value across the link: own value (wall), the same-row neighbour
+        // (velocity boundary) or the neighbour itself; every row index is a
+        // compile-time constant
+        const R v1 = solid ? c1 : (vel ? s.c1[1][EX[k]] : s.c1[r][EX[k]]);
+        const R v2 = solid ? c2 : (vel ? s.c2[1][EX[k]] : s.c2[r][EX[k]]);
+        const R w1 = solid ? mu1 : (vel ? s.mu1[1][EX[k]] : s.mu1[r][EX[k]]);
+        const R w2 = solid ? mu2 : (vel ? s.mu2[1][EX[k]] : s.mu2[r][EX[k]]);
         if (EX[k]) {
             g1x += wgt<R>(k) * R(EX[k]) * v1;
             g2x += wgt<R>(k) * R(EX[k]) * v2;
@@ -246,6 +267,7 @@ __device__ __forceinline__ NodeMacro<R> node_macro(const Stencil<R>& s, const Co
     o.c1 = c1; o.c2 = c2; o.rho = rho; o.itg = R(1) / taug;
     o.mu1 = mu1; o.mu2 = mu2; o.ux = ux; o.uy = uy; o.p = p;
     o.grx = grx; o.gry = gry; o.fx = fx; o.fy = fy; o.fax = ux * a; o.fay = uy * a;
+    o.am = a;
     return o;
 }
 
@@ -268,8 +290,9 @@ __device__ __forceinline__ Stencil<typename Tr<P>::R> tile_stencil(const Smem<P,
 
 // Chemical potentials of Eq. 8 at one fluid node from the c values of its
 // 3x3 neighbourhood (row pointers as in Stencil), with the wetting ghosts of
-// Eq. 42 across links into solid nodes.
-template <typename R>
+// Eq. 42 across links into walls and, across a link into a velocity boundary
+// node, the value of the fluid node inside it (Eq. 53).
+template <typename R, bool VEL = true>
 __device__ __forceinline__ void chem_pot(const R* const* c1r, const R* const* c2r,
                                          const uint8_t* const* mr, const R* mt,
                                          const Consts<R>& c, R& mu1, R& mu2, R& mu3) {
@@ -281,7 +304,11 @@ __device__ __forceinline__ void chem_pot(const R* const* c1r, const R* const* c2
         const int r = EY[k] + 1;
         const int mn = mr[r][EX[k]];
         R n1, n2, n3;
-        if (mn) {
+        if (VEL && ((c.nee >> mn) & 1u)) {
+            n1 = c1r[1][EX[k]];
+            n2 = c2r[1][EX[k]];
+            n3 = R(1) - n1 - n2;
+        } else if (mn) {
             const R* t = &mt[kMatStride * mn];
             const R h1 = t[1] * c1 * c3 + t[0] * c1 * c2;
             const R h2 = -t[0] * c1 * c2 + t[2] * c2 * c3;
@@ -455,7 +482,7 @@ struct Ring {
     R mu3[NM * MW];
     R stash[2][2][18][kTileX];             // [buffer][wave-2][population][lane]
     R mt[kMatStride * (kMaxMaterials + 1)];
-    uint16_t nmask[NM * MW];               // bit k-1: neighbour e_k solid; bit 8: node solid
+    uint32_t nmask[NM * MW];               // neighbour mask (kWallBits, kSelfBit, kVelBits)
     uint8_t m[NR * W];
 };
 
@@ -508,7 +535,7 @@ __device__ __forceinline__ void pull_f(const Grid& g, const Consts<typename Tr<P
 
 // Chemical potentials of one mu-ring node (mu column mcol, c column
 // mcol + 1) and its solid-neighbour mask.
-template <int P>
+template <int P, bool VEL>
 __device__ __forceinline__ void ring_mu(Ring<P>& sm, const Consts<typename Tr<P>::R>& c,
                                         int y, int y0, int mcol) {
     using R = typename Tr<P>::R;
@@ -524,12 +551,14 @@ __device__ __forceinline__ void ring_mu(Ring<P>& sm, const Consts<typename Tr<P>
         c2r[q] = &sm.c2[sc[q] * RG::W + col];
         mr[q] = &sm.m[sc[q] * RG::W + col];
     }
-    unsigned mask = mr[1][0] ? 256u : 0u;
+    unsigned mask = mr[1][0] ? kSelfBit : 0u;
 #pragma unroll
-    for (int k = 1; k < 9; ++k)
-        if (mr[EY[k] + 1][EX[k]]) mask |= 1u << (k - 1);
+    for (int k = 1; k < 9; ++k) {
+        const unsigned mn = mr[EY[k] + 1][EX[k]];
+        if (mn) mask |= (VEL && ((c.nee >> mn) & 1u)) ? 1u << (kVelShift + k) : 1u << (k - 1);
+    }
     R mu1 = R(0), mu2 = R(0), mu3 = R(0);
-    if (!(mask & 256u)) {
+    if (!(mask & kSelfBit)) {
         if (mask == 0) {
             // bulk node: plain Laplacian (Eq. 20b)
             const R a1 = c1r[1][0], a2 = c2r[1][0], a3 = R(1) - a1 - a2;
@@ -547,14 +576,14 @@ __device__ __forceinline__ void ring_mu(Ring<P>& sm, const Consts<typename Tr<P>
             mu2 = c.k12D * (c.lam2 * a2 * (R(1) - a2) * (R(1) - R(2) * a2) - tri) - c.k34D * c.lam2 * l2;
             mu3 = c.k12D * (c.lam3 * a3 * (R(1) - a3) * (R(1) - R(2) * a3) - tri) - c.k34D * c.lam3 * l3;
         } else {
-            chem_pot<R>(c1r, c2r, mr, sm.mt, c, mu1, mu2, mu3);
+            chem_pot<R, VEL>(c1r, c2r, mr, sm.mt, c, mu1, mu2, mu3);
         }
     }
     const int o = mu_slot(y, y0) * RG::MW + mcol;
     sm.mu1[o] = mu1;
     sm.mu2[o] = mu2;
     sm.mu3[o] = mu3;
-    sm.nmask[o] = uint16_t(mask);
+    sm.nmask[o] = mask;
 }
 
 // Phase C of one node: time derivative (Eq. 19 in Eq. 11a), history,
@@ -563,7 +592,7 @@ __device__ __forceinline__ void ring_mu(Ring<P>& sm, const Consts<typename Tr<P>
 // for a node next to solids, half-way bounce-back into the solid slots
 // (Eq. 44) with the moving-wall term -2 w_k a e_k.u_w / c_s^2 (a = c_i for
 // f^i, rho for g).
-template <int P>
+template <int P, bool VEL>
 __device__ __forceinline__ void node_update(const Grid& g, const Consts<typename Tr<P>::R>& c,
                                             const Stencil<typename Tr<P>::R>& s,
                                             const typename Tr<P>::R* mt, const Nb32& nb,
@@ -574,7 +603,7 @@ __device__ __forceinline__ void node_update(const Grid& g, const Consts<typename
                                             rsrc_t hist, unsigned hstride) {
     using R = typename Tr<P>::R;
     using HT = typename Tr<P>::H;
-    const NodeMacro<R> o = node_macro<R, true>(s, c, gg, mask);
+    const NodeMacro<R> o = node_macro<R, true, VEL>(s, c, gg, mask);
     const R d1x = o.c1 * o.ux - ho[0] * ho[2], d1y = o.c1 * o.uy - ho[0] * ho[3];
     const R d2x = o.c2 * o.ux - ho[1] * ho[2], d2y = o.c2 * o.uy - ho[1] * ho[3];
     // byte offsets of this node's slots, or kDiscard for a lane without a
@@ -619,6 +648,51 @@ __device__ __forceinline__ void node_update(const Grid& g, const Consts<typename
     const R G0 = R(3) * fsg * (o.ux * o.fx + o.uy * o.fy);
     const R Pg = R(3) * o.itg * o.p;
     const R Rg = o.itg * o.rho;
+    // Velocity boundary node x_u = x + e_kn directly above (kn = 2) or below
+    // (kn = 4) this node.  Its populations are its equilibrium plus this
+    // node's non-equilibrium part (Eqs. 51-53): with every quantity but u
+    // taken from this node, f^i_k(x_u) = f^i_k + 3 w_k c_i e_k.(u_w - u) and
+    // g_k(x_u) = g_k + rho (s_k(u_w) - s_k(u)).  x_u collides like any node
+    // (Eq. 45) with the sources of Eq. 11 at u = u_w: V_i and G1, G0 above
+    // with u_w, D_i = u_w (c_i - c_i^old).  Only the three populations that
+    // stream back into the fluid are stored.  Done before this node's own
+    // stores so that nothing extra stays live across them.
+    if (VEL && live && (mask & kVelBits)) {
+#pragma unroll
+        for (int kn = 2; kn <= 4; kn += 2) {
+            if (!(mask & (1u << (kVelShift + kn)))) continue;
+            const int mn = s.m[EY[kn] + 1][0];
+            const R uwx = mt[kMatStride * mn + 3], uwy = mt[kMatStride * mn + 4];
+            const unsigned sn = nb.dn(kn);
+            const unsigned sb = sn * unsigned(sizeof(typename Tr<P>::S)), s4 = sn * 4u;
+            // e_k.V_i at u_w is 3 e_k.u_w a_i with a_i = c_i / tau_i + (1 - 1/(2 tau_i))
+            // (c_i - c_i^old); e_k.G1 = 3 fsg e_k.F + 3 am e_k.u_w, G0 = 3 fsg u_w.F
+            const R a1 = c.itau1 * o.c1 + c.fs1 * (o.c1 - ho[0]);
+            const R a2 = c.itau2 * o.c2 + c.fs2 * (o.c2 - ho[1]);
+            const R wF = uwx * o.fx + uwy * o.fy;
+            const R wA = uwx * Ax + uwy * Ay;
+            const R ww = uwx * uwx + uwy * uwy;
+#pragma unroll
+            for (int k = 1; k < 9; ++k) {
+                if (EY[k] != -EY[kn]) continue;
+                const R w = wgt<R>(k);
+                const R eu = R(EX[k]) * o.ux + R(EY[k]) * o.uy;
+                const R ew = R(EX[k]) * uwx + R(EY[k]) * uwy;
+                const R sku = w * (eu * (R(3) + R(4.5) * eu) - R(1.5) * uu);
+                const R skw = w * (ew * (R(3) + R(4.5) * ew) - R(1.5) * ww);
+                const R eA = R(EX[k]) * Ax + R(EY[k]) * Ay;
+                const R eF = R(EX[k]) * o.fx + R(EY[k]) * o.fy;
+                const R f1u = om1 * (f1[k] + R(3) * w * o.c1 * (ew - eu)) + w * (P1 + R(3) * ew * a1);
+                const R f2u = om2 * (f2[k] + R(3) * w * o.c2 * (ew - eu)) + w * (P2 + R(3) * ew * a2);
+                const R gu = omg * (gg[k] + o.rho * (skw - sku)) +
+                             w * (Pg + R(3) * (fsg * (eF - wF) + o.am * ew)) +
+                             skw * (Rg + fsg * (eA - wA));
+                bst<P>(dst, c, 0, k, sb, s4, f1u);
+                bst<P>(dst, c, 1, k, sb, s4, f2u);
+                bst<P>(dst, c, 2, k, sb, s4, gu);
+            }
+        }
+    }
     R g2[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
@@ -642,7 +716,7 @@ __device__ __forceinline__ void node_update(const Grid& g, const Consts<typename
         bst<P>(dst, c, 1, k, ob, o4, f2[k]);
         bst<P>(dst, c, 2, k, ob, o4, g2[k]);
     }
-    if (live && (mask & 255u)) {
+    if (live && (mask & kWallBits)) {
 #pragma unroll
         for (int k = 1; k < 9; ++k) {
             if (mask & (1u << (k - 1))) {
@@ -657,10 +731,11 @@ __device__ __forceinline__ void node_update(const Grid& g, const Consts<typename
             }
         }
     }
+
 }
 
 // One strip (tile t) of one lattice.
-template <int P>
+template <int P, bool VEL>
 __device__ __forceinline__ void step_tile(const Grid& g, const Consts<typename Tr<P>::R>& c,
                                           const uint8_t* __restrict__ mat,
                                           const double* __restrict__ mtab, PopBuf srcb,
@@ -688,7 +763,7 @@ __device__ __forceinline__ void step_tile(const Grid& g, const Consts<typename T
             const int r = threadIdx.x / RG::MW;
             const int mcol = threadIdx.x - r * RG::MW;
             const int y = Y + 1 + r;
-            if (y >= y0 - 1) ring_mu<P>(sm, c, y, y0, mcol);  // prologue: rows below y0-1 lack neighbours
+            if (y >= y0 - 1) ring_mu<P, VEL>(sm, c, y, y0, mcol);  // prologue: rows below y0-1 lack neighbours
         }
     };
 
@@ -817,8 +892,8 @@ __device__ __forceinline__ void step_tile(const Grid& g, const Consts<typename T
                 s.mu2[r] = &sm.mu2[ml[r] * RG::MW + lane + 1];
             }
             s.mu3 = sm.mu3[ml[1] * RG::MW + lane + 1];
-            const unsigned mask = out_lane ? unsigned(sm.nmask[ml[1] * RG::MW + lane + 1]) : 256u;
-            const bool live = out_lane && yo < y0 + rows && !(mask & 256u);
+            const unsigned mask = out_lane ? sm.nmask[ml[1] * RG::MW + lane + 1] : kSelfBit;
+            const bool live = out_lane && yo < y0 + rows && !(mask & kSelfBit);
             if (w >= 2) {
 #pragma unroll
                 for (int k = 0; k < 9; ++k) {
@@ -826,8 +901,8 @@ __device__ __forceinline__ void step_tile(const Grid& g, const Consts<typename T
                     cf2[k] = sm.stash[(it - 1) & 1][w - 2][9 + k][lane];
                 }
             }
-            node_update<P>(g, c, s, sm.mt, nb, idx, live, mask, cf1, cf2, gg, ho, dst, hist,
-                           hstride);
+            node_update<P, VEL>(g, c, s, sm.mt, nb, idx, live, mask, cf1, cf2, gg, ho, dst, hist,
+                                hstride);
         }
         // phase A of the next iteration (after the last one its loads are
         // all out of range)
@@ -842,8 +917,9 @@ __device__ __forceinline__ void step_tile(const Grid& g, const Consts<typename T
 // binary search.  parity selects which of each lattice's two population
 // buffers is the source in this step.  A lattice's strips are computed by the
 // same code whatever else is in the table, so results do not depend on the
-// batch.
-template <int P>
+// batch.  VEL selects the variant that handles velocity boundary nodes
+// (needed when any lattice of the table has them).
+template <int P, bool VEL>
 __global__ __launch_bounds__(kStepThreads)
 __attribute__((amdgpu_waves_per_eu(P == P64 ? 2 : 4)))
 void step_kernel(const unsigned char* __restrict__ descs, int ndesc, int total_tiles, int parity) {
@@ -864,7 +940,7 @@ void step_kernel(const unsigned char* __restrict__ descs, int ndesc, int total_t
     const Grid g = d.g;
     const Consts<typename Tr<P>::R> c = d.c;
     const int sb = (d.cur + parity) & 1;
-    step_tile<P>(g, c, d.mat, d.mtab, d.buf[sb], d.buf[sb ^ 1], d.hist, L - d.tile_begin, sm);
+    step_tile<P, VEL>(g, c, d.mat, d.mtab, d.buf[sb], d.buf[sb ^ 1], d.hist, L - d.tile_begin, sm);
 }
 
 // ------------------------------------------------------------------- init
@@ -1067,9 +1143,14 @@ template <int P>
 using CT = Consts<typename Tr<P>::R>;
 
 template <int P>
-hipError_t step_p(const void* descs, int ndesc, int total_tiles, int parity, hipStream_t s) {
-    hipLaunchKernelGGL((step_kernel<P>), dim3(total_tiles), dim3(kStepThreads), 0, s,
-                       static_cast<const unsigned char*>(descs), ndesc, total_tiles, parity);
+hipError_t step_p(bool vel, const void* descs, int ndesc, int total_tiles, int parity,
+                  hipStream_t s) {
+    if (vel)
+        hipLaunchKernelGGL((step_kernel<P, true>), dim3(total_tiles), dim3(kStepThreads), 0, s,
+                           static_cast<const unsigned char*>(descs), ndesc, total_tiles, parity);
+    else
+        hipLaunchKernelGGL((step_kernel<P, false>), dim3(total_tiles), dim3(kStepThreads), 0, s,
+                           static_cast<const unsigned char*>(descs), ndesc, total_tiles, parity);
     return hipGetLastError();
 }
 
@@ -1077,12 +1158,12 @@ constexpr int kAuxRows = 8;  // tile rows of the init / readout kernels
 
 }  // namespace
 
-hipError_t launch_step(int prec, const void* descs, int ndesc, int total_tiles, int parity,
-                       hipStream_t s) {
+hipError_t launch_step(int prec, bool vel, const void* descs, int ndesc, int total_tiles,
+                       int parity, hipStream_t s) {
     switch (prec) {
-        case P64: return step_p<P64>(descs, ndesc, total_tiles, parity, s);
-        case P32: return step_p<P32>(descs, ndesc, total_tiles, parity, s);
-        case P16: return step_p<P16>(descs, ndesc, total_tiles, parity, s);
+        case P64: return step_p<P64>(vel, descs, ndesc, total_tiles, parity, s);
+        case P32: return step_p<P32>(vel, descs, ndesc, total_tiles, parity, s);
+        case P16: return step_p<P16>(vel, descs, ndesc, total_tiles, parity, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -41,7 +41,10 @@ class tlb_fluid(C.Structure):
 
 class tlb_material(C.Structure):
     _fields_ = [("theta13_deg", C.c_double), ("theta23_deg", C.c_double),
-                ("wall_u", C.c_double * 2)]
+                ("wall_u", C.c_double * 2), ("kind", C.c_int)]
+
+
+TLB_WALL, TLB_VELOCITY = 0, 1
 
 
 class tlb_request(C.Structure):
@@ -143,6 +146,7 @@ def make_materials(mats):
         arr[i].theta23_deg = m["theta23"]
         wu = m.get("wall_u", (0.0, 0.0))
         arr[i].wall_u[0], arr[i].wall_u[1] = wu[0], wu[1]
+        arr[i].kind = int(m.get("kind", TLB_WALL))
     return arr
 
 
