@@ -1,7 +1,8 @@
 """Benchmark of the fused ternary wetting LB step on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32]
-                    [--workload cylinder_impact] [--no-cpu] [--quick]
+                    [--workload cylinder_impact] [--only] [--no-cpu]
+                    [--no-serving] [--no-sweep] [--copy-calibration MIB]
 
 Workload: the compound-drop / cylinder-impact lattice, 1024 x 2048 nodes,
 staircase cylinder of radius 128 (We = 10, theta = 90 deg), FP32
@@ -89,6 +90,33 @@ def time_precision(tlb, torch, problem, precision, steps, warmup):
     m = s.mass()
     del s
     return dt, kms, m
+
+
+def bw_sweep_leg(tlb, torch, sizes=((1024, 2048), (2048, 2048), (4096, 4096)), steps=500):
+    """The cylinder layout without a drop at three sizes and every storage
+    precision: step-kernel time from HIP events on the solver's stream over
+    `steps` launches, and the algorithmic bandwidth it implies.  The FP64
+    and FP32 working sets exceed the 256 MB MALL at every size."""
+    from paper_1710_09534_amd import workloads as W
+    out = []
+    for nx, ny in sizes:
+        prob = W.bandwidth_case(nx, ny)
+        n = nx * ny
+        for prec in ("fp64", "fp32", "fp16dev"):
+            s = tlb.from_problem(prob, prec)
+            s.set_check_interval(0)
+            s.time_steps(20)
+            kms = s.time_steps(steps)
+            del s
+            torch.cuda.synchronize()
+            gbs = algorithmic_bytes(prob, prec) / (kms * 1e-3) / 1e9
+            out.append({"size": "%dx%d" % (nx, ny), "precision": prec,
+                        "kernel_ms": round(kms, 4), "mlups": round(n / kms / 1e3, 1),
+                        "algorithmic_gbs": round(gbs, 1),
+                        "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)})
+            print("# bw sweep %s %s %.4f ms %.0f MLUPS %.0f GB/s" %
+                  (out[-1]["size"], prec, kms, out[-1]["mlups"], gbs), file=sys.stderr, flush=True)
+    return out
 
 
 def batching_leg(tlb, torch, precision="fp32", n_lattices=256, size=64, steps=200):
@@ -221,6 +249,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only", action="store_true", help="time the headline precision only")
     ap.add_argument("--no-serving", action="store_true", help="skip the batching and serving legs")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the bandwidth sweep leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB, 10 times (counter scale)")
     args = ap.parse_args()
@@ -298,6 +327,8 @@ def main():
                      "algorithmic_bytes_per_launch": alg},
         "precisions": table,
     }
+    if not (args.only or args.no_sweep):
+        out["bw_sweep"] = bw_sweep_leg(tlb, torch)
     if not (args.only or args.no_serving):
         out["batching"] = batching_leg(tlb, torch)
         print("# batching: %s" % out["batching"], file=sys.stderr, flush=True)

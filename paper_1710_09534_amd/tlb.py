@@ -179,10 +179,12 @@ class Solver:
     def __del__(self):
         self.destroy()
 
-    def destroy(self):
+    def destroy(self, _lib=lib):
+        # _lib is bound at definition time: module globals may already be
+        # cleared when this runs during interpreter shutdown
         ctx = getattr(self, "ctx", None)
         if ctx is not None and ctx.value:
-            lib.tlb_destroy(ctx)
+            _lib.tlb_destroy(ctx)
         self.ctx = None
 
     @property
@@ -300,10 +302,10 @@ class Batch:
     def sync(self):
         self._check(lib.tlb_batch_sync(self.h))
 
-    def __del__(self):
+    def __del__(self, _lib=lib):
         h = getattr(self, "h", None)
         if h is not None and h.value:
-            lib.tlb_batch_destroy(h)
+            _lib.tlb_batch_destroy(h)
             self.h = None
 
 
@@ -401,10 +403,10 @@ class Server:
         self._check(lib.tlb_server_stats(self.h, C.byref(c)))
         return {f: getattr(c, f) for f, _ in tlb_server_counters._fields_}
 
-    def close(self):
+    def close(self, _lib=lib):
         h = getattr(self, "h", None)
         if h is not None and h.value:
-            lib.tlb_server_destroy(h)
+            _lib.tlb_server_destroy(h)
             self.h = None
 
     def __del__(self):

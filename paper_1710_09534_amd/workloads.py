@@ -250,6 +250,24 @@ def nee_shear(nx=400, ny=150, U0=0.1, R_core=25.5, R_shell=60.0, offset=7.5,
                     core, np.clip(shell, 0.0, None), steps=steps, U0=U0)
 
 
+def gravity_puddles(g=4e-5, nx=600, ny=150, R=60.0, theta=90.0, sigma=0.1, M0=0.01,
+                    steps=200000):
+    """Two drops (densities 10 and 5 in an ambient fluid of density 1) on a
+    wall under gravity G = (0, -rho g) (Sec. III.A): drops of radius
+    R = nx/10 centred on the wall surface at x = nx/4 and 3nx/4, L = 4W,
+    sigma = 0.1 for every pair, theta13 = theta23 = theta, tau = 0.8,
+    M0 = 0.01; walls in rows 0 (wetting) and ny-1 (neutral)."""
+    D = 4.0
+    c1 = tanh_drop(nx, ny, 0.25 * nx, 0.5, R, D)
+    c2 = tanh_drop(nx, ny, 0.75 * nx, 0.5, R, D)
+    mask = channel_mask(nx, ny)
+    mats = [material(theta, theta), material(90.0, 90.0)]
+    fl = fluid(sigma=(sigma, sigma, sigma), D=D, M0=M0, tau=(0.8, 0.8), rho=(10, 5, 1),
+               nu=(0.1, 0.1, 0.1), gravity=(0.0, -g))
+    return _problem("gravity_puddles_%dx%d_g%g" % (nx, ny, g), nx, ny, fl, (1, 0), mask, mats,
+                    c1, c2, steps=steps, g=g, R=R)
+
+
 def cylinder_impact(We=10.0, theta=90.0, nx=1024, ny=2048, R_cyl=128.0, R_shell=96.0,
                     R_core=48.0, sigma=5e-3, steps=100000):
     """Compound drop (phase-1 core, phase-2 shell) falling onto a staircase

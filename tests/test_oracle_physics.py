@@ -172,3 +172,24 @@ def test_de_gennes_cap(theta):
     Ls_th, Hd_th = 2 * R * k * math.sin(te), R * k * (1 - math.cos(te))
     assert abs(th_n - theta) < 3.0, (th_n, theta)
     assert abs(Ls - Ls_th) < 0.06 * Ls_th and abs(Hd - Hd_th) < 0.06 * Hd_th, (Ls, Ls_th, Hd, Hd_th)
+
+
+def test_hydrostatic_pressure_in_stratified_layers():
+    """Three flat layers (densities 10, 5, 1, heaviest at the bottom) at rest
+    under G = (0, -rho g): in each bulk layer the pressure of Eq. 13c falls
+    with slope -rho_i g (the momentum balance grad p = F_s + G with F_s = 0
+    away from interfaces), and the fluid stays at rest."""
+    nx, ny, g, D = 4, 48, 1e-5, 4.0
+    y = np.arange(ny)[:, None] + np.zeros((1, nx))
+    c1 = 0.5 - 0.5 * np.tanh(2 * (y - 16.0) / D)
+    c2 = (0.5 - 0.5 * np.tanh(2 * (y - 32.0) / D)) - c1
+    fl = W.fluid(sigma=(1e-3, 1e-3, 1e-3), M0=1e-4, rho=(10, 5, 1), gravity=(0, -g),
+                 tau=(1.0, 1.0), nu=(1 / 6, 1 / 6, 1 / 6))
+    p = W._problem("hydrostatic", nx, ny, fl, (1, 0), W.channel_mask(nx, ny),
+                   [W.material(90, 90), W.material(90, 90)], c1, c2)
+    f = _run(p, 20000).fields()
+    pc = f["p"][:, 0]
+    for (a, b, rho) in [(3, 10, 10.0), (22, 27, 5.0), (38, 45, 1.0)]:
+        slope = np.polyfit(np.arange(a, b), pc[a:b], 1)[0]
+        assert abs(slope + rho * g) <= 0.01 * rho * g, (rho, slope)
+    assert np.abs(f["ux"]).max() < 1e-12 and np.abs(f["uy"]).max() < 1e-6
