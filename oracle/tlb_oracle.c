@@ -94,10 +94,13 @@ int orc_params(const orc_fluid* fl, orc_derived* out) {
     out->M[1] = fl->M0 / l2;
     out->eta[0] = out->M[0] / (CS2 * (fl->tau1 - 0.5));
     out->eta[1] = out->M[1] / (CS2 * (fl->tau2 - 0.5));
-    /* admissibility printed with Eq. 7: lambda_i > 0 and lambda_i > lambda_T/2 */
+    /* lambda_i > 0 (M_i = M0/lambda_i and Eq. 9 need it); the condition
+     * lambda_i > lambda_T/2 is stated for the energy with lambda = 0, so it
+     * is required only then */
+    if (!(fl->lambda >= 0.0)) return -1;
     for (int i = 0; i < 3; ++i) {
         if (!(out->lambda[i] > 0.0)) return -1;
-        if (!(out->lambda[i] > 0.5 * out->lambdaT)) return -1;
+        if (fl->lambda == 0.0 && !(out->lambda[i] > 0.5 * out->lambdaT)) return -1;
     }
     return 0;
 }
@@ -126,7 +129,10 @@ void orc_wetting_ghost(double D, double cos12, double cos13, double cos23,
     out[2] = c3 + (4.0 / D) * h3;
 }
 
-/* Eq. 8 (bulk energy Eq. 5 with lambda = 0), i = 1, 2, 3 */
+/* Eq. 8 (bulk energy Eq. 5 with lambda = 0), i = 1, 2, 3, plus, for
+ * lambda > 0, the part of Eq. 6 that comes from the lambda c1^2 c2^2 c3^2 term
+ * of Eq. 5: with dP/dc_i = 2 lambda c_i c_j^2 c_k^2 ({i,j,k} = {1,2,3}),
+ * (4 lambda_T / D) sum_{j != i} (dP/dc_i - dP/dc_j) / lambda_j. */
 void orc_chem_potential(const orc_fluid* fl, double c1, double c2,
                         double lap1, double lap2, double lap3, double mu[3]) {
     orc_derived d;
@@ -139,6 +145,21 @@ void orc_chem_potential(const orc_fluid* fl, double c1, double c2,
         double bulk = d.lambda[i] * c[i] * (1.0 - c[i]) * (1.0 - 2.0 * c[i])
                     - 2.0 * d.lambdaT * c1 * c2 * (1.0 - c1 - c2);
         mu[i] = (12.0 / D) * bulk - 0.75 * D * d.lambda[i] * lap[i];
+    }
+    if (fl->lambda != 0.0) {
+        double dP[3];
+        for (int i = 0; i < 3; ++i) {
+            double prod = 1.0;
+            for (int j = 0; j < 3; ++j)
+                if (j != i) prod *= c[j] * c[j];
+            dP[i] = 2.0 * fl->lambda * c[i] * prod;
+        }
+        for (int i = 0; i < 3; ++i) {
+            double acc = 0.0;
+            for (int j = 0; j < 3; ++j)
+                if (j != i) acc += (dP[i] - dP[j]) / d.lambda[j];
+            mu[i] += 4.0 * d.lambdaT / D * acc;
+        }
     }
 }
 

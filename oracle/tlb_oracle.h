@@ -35,6 +35,8 @@ typedef struct {
     double tau1, tau2;                /* Eq. 1a */
     double rho[3], nu[3];             /* Eqs. 14-15 */
     double gravity[2];                /* body force G = rho * gravity */
+    double lambda;                    /* coefficient of the c1^2 c2^2 c3^2 term of the
+                                         bulk energy, Eq. 5 (>= 0; 0 gives Eq. 8) */
 } orc_fluid;
 
 /* material kinds */
@@ -86,7 +88,8 @@ int    orc_cos12(const orc_fluid* fl, double theta13_deg, double theta23_deg, do
 /* ghost order parameters of Eq. 42 for one fluid node and one solid link */
 void   orc_wetting_ghost(double D, double cos12, double cos13, double cos23,
                          double c1, double c2, double out[3]);
-/* chemical potentials of Eq. 8 from c and the Laplacians of c */
+/* chemical potentials of Eq. 6 (Eq. 8 when lambda = 0) from c and the
+ * Laplacians of c */
 void   orc_chem_potential(const orc_fluid* fl, double c1, double c2,
                           double lap1, double lap2, double lap3, double mu[3]);
 /* f^{i,eq} (Eq. 2a) and g^eq (Eq. 2b, Eq. 4) */

@@ -93,11 +93,11 @@ def cylinder_mask(nx, ny, xc, yc, R, material=1):
 
 
 def fluid(sigma=(1e-3, 1e-3, 1e-3), D=4.0, M0=1e-4, tau=(0.8, 0.8), rho=(1.0, 1.0, 1.0),
-          nu=(0.1, 0.1, 0.1), gravity=(0.0, 0.0)) -> dict:
+          nu=(0.1, 0.1, 0.1), gravity=(0.0, 0.0), lam=0.0) -> dict:
     return {"sigma12": float(sigma[0]), "sigma13": float(sigma[1]), "sigma23": float(sigma[2]),
             "D": float(D), "M0": float(M0), "tau1": float(tau[0]), "tau2": float(tau[1]),
             "rho": [float(r) for r in rho], "nu": [float(v) for v in nu],
-            "gravity": [float(g) for g in gravity]}
+            "gravity": [float(g) for g in gravity], "lambda": float(lam)}
 
 
 WALL, VELOCITY = 0, 1     # material kinds
