@@ -68,6 +68,9 @@ typedef struct {
     double rho[3], nu[3];             /* phase densities / kinematic viscosities, Eqs. 14-15;
                                          local tau_g = nu/c_s^2 + 1/2, Eq. 18b */
     double gravity[2];                /* body force G = rho * gravity (Sec. III.A) */
+    double lambda;                    /* coefficient of lambda c1^2 c2^2 c3^2 in the bulk
+                                         energy, Eq. 5 (>= 0): the chemical potentials follow
+                                         Eq. 6; 0 gives the paper's Eq. 8 */
 } tlb_fluid;
 
 /* Material kinds. */
@@ -111,8 +114,9 @@ size_t tlb_workspace_bytes(int nx, int ny, tlb_precision p);
 /* Create a context on a caller-owned device workspace (at least
  * tlb_workspace_bytes, 256-byte aligned, alive until tlb_destroy) and a HIP
  * stream (hipStream_t, NULL = default stream).  Validates the fluid
- * parameters (Eqs. 7, 9, 18): lambda_i > 0 and lambda_i > lambda_T/2,
- * tau_i > 1/2, D > 0, M0 > 0, rho_i > 0, nu_i > 0 (else TLB_EPARAM).
+ * parameters (Eqs. 7, 9, 18): lambda_i > 0, lambda >= 0, lambda_i >
+ * lambda_T/2 when lambda = 0 (the range stated for that energy), tau_i > 1/2,
+ * D > 0, M0 > 0, rho_i > 0, nu_i > 0 (else TLB_EPARAM).
  * Each family of 9 population planes must stay below 2 GiB (FP64: about
  * 29.8 M nodes, e.g. 5400 x 5400; else TLB_EINVAL).
  * The library owns *out until tlb_destroy. */

@@ -134,6 +134,10 @@ void fill_consts(Consts<R>& k, const tlb_ctx* c) {
     k.k4D = R(4.0 / f.D);
     k.gx = R(f.gravity[0]);
     k.gy = R(f.gravity[1]);
+    k.kB = R(8.0 * f.lambda * c->lambdaT / f.D);
+    k.il1 = R(1.0 / c->lambda[0]);
+    k.il2 = R(1.0 / c->lambda[1]);
+    k.il3 = R(1.0 / c->lambda[2]);
     for (int i = 0; i < 3; ++i) {
         k.scale[i] = 1.0f;
         k.iscale[i] = 1.0f;
@@ -241,9 +245,12 @@ tlb_status tlb_create(int nx, int ny, tlb_precision p, const tlb_fluid* fl, void
     for (double l : lam)
         if (!(l > 0.0)) return fail(nullptr, TLB_EPARAM, "surface tensions give lambda_i <= 0");
     double lamT = 3.0 / (1.0 / lam[0] + 1.0 / lam[1] + 1.0 / lam[2]);
-    for (double l : lam)
-        if (!(l > 0.5 * lamT))
-            return fail(nullptr, TLB_EPARAM, "surface tensions give lambda_i <= lambda_T/2");
+    if (!(fl->lambda >= 0.0) || !std::isfinite(fl->lambda))
+        return fail(nullptr, TLB_EPARAM, "lambda (Eq. 5) must be finite and >= 0");
+    if (fl->lambda == 0.0)
+        for (double l : lam)
+            if (!(l > 0.5 * lamT))
+                return fail(nullptr, TLB_EPARAM, "surface tensions give lambda_i <= lambda_T/2");
     if (!(fl->D > 0.0) || !(fl->M0 > 0.0)) return fail(nullptr, TLB_EPARAM, "D and M0 must be > 0");
     if (!(fl->tau1 > 0.5) || !(fl->tau2 > 0.5)) return fail(nullptr, TLB_EPARAM, "tau_i must be > 1/2");
     for (int i = 0; i < 3; ++i)
@@ -413,10 +420,15 @@ tlb_status tlb_init_fields(tlb_ctx* c, const double* c1, const double* c2, const
     return upload_desc(c);
 }
 
+// optional step-kernel parts this lattice needs (launch_step's features)
+static unsigned features(const tlb_ctx* c) {
+    return (c->c64.nee != 0u ? 1u : 0u) | (c->fl.lambda != 0.0 ? 2u : 0u);
+}
+
 static tlb_status step_impl(tlb_ctx* c, int64_t nsteps, bool checks) {
     for (int64_t s = 0; s < nsteps; ++s) {
-        hipError_t e = launch_step(c->prec, c->c64.nee != 0u, c->ws + c->L.off_desc, 1,
-                                   ntiles(c), c->cur, c->stream);
+        hipError_t e = launch_step(c->prec, features(c), c->ws + c->L.off_desc, 1, ntiles(c),
+                                   c->cur, c->stream);
         if (e != hipSuccess) return dev_fail(c, e, "step kernel");
         c->cur = 1 - c->cur;
         ++c->steps;
@@ -574,17 +586,20 @@ tlb_status tlb_checkpoint_load(tlb_ctx* c, const void* buf) {
 tlb_status tlb_time_steps(tlb_ctx* c, int64_t nsteps, double* ms) {
     if (!c || !ms || nsteps <= 0) return fail(c, TLB_EINVAL, "bad arguments");
     if (!c->inited) return fail(c, TLB_ESTATE, "init_fields must precede time_steps");
-    hipEvent_t a, b;
-    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
-        return fail(c, TLB_EDEVICE, "event create");
-    hipEventRecord(a, c->stream);
-    tlb_status st = step_impl(c, nsteps, false);
-    hipEventRecord(b, c->stream);
-    hipError_t e = hipEventSynchronize(b);
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (e == hipSuccess) e = hipEventRecord(a, c->stream);
+    tlb_status st = TLB_OK;
+    if (e == hipSuccess) {
+        st = step_impl(c, nsteps, false);
+        e = hipEventRecord(b, c->stream);
+    }
+    if (e == hipSuccess) e = hipEventSynchronize(b);
     float t = 0.0f;
     if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
-    hipEventDestroy(a);
-    hipEventDestroy(b);
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
     if (st != TLB_OK) return st;
     if (e != hipSuccess) return dev_fail(c, e, "time_steps");
     *ms = double(t) / double(nsteps);
@@ -604,7 +619,7 @@ struct tlb_batch {
     std::vector<int> base_cur;         // each member's cur when the table was written
     std::vector<unsigned char> host;   // staged table
     int total_tiles = 0;
-    bool vel = false;                  // some member has velocity boundary nodes
+    unsigned features = 0;             // union of the members' step-kernel features
     int parity = 0;                    // parity of the next step relative to the table
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -619,8 +634,8 @@ tlb_status bfail(tlb_batch* b, tlb_status s, const std::string& m) {
     return s;
 }
 void drop_graph(tlb_batch* b) {
-    if (b->exec) hipGraphExecDestroy(b->exec);
-    if (b->graph) hipGraphDestroy(b->graph);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
     b->exec = nullptr;
     b->graph = nullptr;
     b->graph_steps = 0;
@@ -654,11 +669,11 @@ tlb_status tlb_batch_set(tlb_batch* b, tlb_ctx* const* ctxs, int n) {
     if (!b || (n > 0 && !ctxs) || n < 0) return bfail(b, TLB_EINVAL, "null batch or contexts");
     if (n > b->cap) return bfail(b, TLB_EINVAL, "more lattices than the batch capacity");
     int prec = -1, tiles = 0;
-    bool vel = false;
+    unsigned feat = 0;
     for (int i = 0; i < n; ++i) {
         tlb_ctx* c = ctxs[i];
         if (!c) return bfail(b, TLB_EINVAL, "null context in batch");
-        vel = vel || c->c64.nee != 0u;
+        feat |= features(c);
         if (!c->inited) return bfail(b, TLB_ESTATE, "every context must be initialised");
         if (c->diverged) return bfail(b, TLB_EDIVERGED, "a context has diverged");
         if (prec >= 0 && c->prec != prec) return bfail(b, TLB_EINVAL, "mixed precisions in batch");
@@ -689,7 +704,7 @@ tlb_status tlb_batch_set(tlb_batch* b, tlb_ctx* const* ctxs, int n) {
     for (int i = 0; i < n; ++i) b->base_cur[size_t(i)] = ctxs[i]->cur;
     b->prec = prec;
     b->total_tiles = tiles;
-    b->vel = vel;
+    b->features = feat;
     b->parity = 0;
     return TLB_OK;
 }
@@ -703,7 +718,7 @@ tlb_status tlb_batch_use_graph(tlb_batch* b, int steps) {
     if (e != hipSuccess) return bfail(b, TLB_EDEVICE, std::string("begin capture: ") + hipGetErrorString(e));
     hipError_t le = hipSuccess;
     for (int s = 0; s < steps && le == hipSuccess; ++s)
-        le = launch_step(b->prec, b->vel, b->dev, int(b->ctxs.size()), b->total_tiles, s & 1,
+        le = launch_step(b->prec, b->features, b->dev, int(b->ctxs.size()), b->total_tiles, s & 1,
                          b->stream);
     e = hipStreamEndCapture(b->stream, &b->graph);
     if (le != hipSuccess || e != hipSuccess) {
@@ -738,7 +753,7 @@ tlb_status tlb_batch_step(tlb_batch* b, int64_t nsteps) {
             done += b->graph_steps;
             continue;   // even step count: parity unchanged
         }
-        e = launch_step(b->prec, b->vel, b->dev, nd, b->total_tiles, b->parity, b->stream);
+        e = launch_step(b->prec, b->features, b->dev, nd, b->total_tiles, b->parity, b->stream);
         if (e != hipSuccess) return bfail(b, TLB_EDEVICE, std::string("batch step: ") + hipGetErrorString(e));
         b->parity ^= 1;
         ++done;
@@ -763,7 +778,7 @@ const char* tlb_batch_last_error(const tlb_batch* b) {
 
 void tlb_batch_destroy(tlb_batch* b) {
     if (!b) return;
-    hipStreamSynchronize(b->stream);
+    (void)hipStreamSynchronize(b->stream);
     drop_graph(b);
     delete b;
 }
@@ -801,9 +816,10 @@ const char* tlb_last_error(const tlb_ctx* c) {
 
 void tlb_destroy(tlb_ctx* c) {
     if (!c) return;
-    if (c->stream) hipStreamSynchronize(c->stream);
-    else hipDeviceSynchronize();
-    if (c->health) hipHostFree(c->health);
+    // teardown: nothing to report to, so errors are dropped
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    if (c->health) (void)hipHostFree(c->health);
     delete c;
 }
 

@@ -41,6 +41,10 @@ struct Consts {
     float scale[3], iscale[3];   // P16 storage scales per family
     unsigned nee;                // bit m set: material m is a velocity boundary
                                  // (non-equilibrium extrapolation, Eqs. 51-53)
+    // fields used only by optional kernel parts stay last, so that adding
+    // them leaves the layout the plain step kernel loads unchanged
+    R kB;                        // 8 lambda lambda_T / D (lambda c1^2 c2^2 c3^2 term of Eq. 5)
+    R il1, il2, il3;             // 1 / lambda_i
 };
 
 // Per-material table (device memory, FP64): for material id m in 0..15 the
@@ -75,9 +79,10 @@ constexpr size_t kDescBytes = 512;  // >= sizeof(LatDesc), a multiple of 256
 // host-side launchers (tlb_kernels.hip)
 // Step kernel over a device table of descriptors (LatDesc<double,double> for
 // P64, LatDesc<float,float> otherwise); total_tiles = sum of strip counts;
-// vel: some lattice of the table has velocity boundary nodes.
-hipError_t launch_step(int prec, bool vel, const void* descs, int ndesc, int total_tiles,
-                       int parity, hipStream_t s);
+// features: bit 0 some lattice of the table has velocity boundary nodes,
+// bit 1 some lattice has a bulk energy with lambda > 0.
+hipError_t launch_step(int prec, unsigned features, const void* descs, int ndesc,
+                       int total_tiles, int parity, hipStream_t s);
 // `consts` points to a host Consts<double> (P64) or Consts<float> (P32, P16);
 // `mtab` to the device material table.
 hipError_t launch_init(int prec, const Grid& g, const void* consts, const uint8_t* mat,

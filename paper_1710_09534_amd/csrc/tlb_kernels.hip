@@ -182,6 +182,11 @@ constexpr unsigned kSelfBit = 0x100u;
 constexpr unsigned kVelShift = 15u;
 constexpr unsigned kVelBits = 0xFFu << 16;
 
+// Optional parts of the step, selected per launch at compile time so that a
+// lattice that does not use them runs code without them.
+constexpr unsigned kFeatVel = 1u;   // velocity boundary nodes (Eqs. 51-53)
+constexpr unsigned kFeatLam = 2u;   // bulk energy with lambda > 0 (Eqs. 5-6)
+
 // LDS neighbourhood of one node: row pointers for y-1, y, y+1 (index 0..2),
 // each already offset to the node's column.
 template <typename R>
@@ -288,11 +293,28 @@ __device__ __forceinline__ Stencil<typename Tr<P>::R> tile_stencil(const Smem<P,
     return s;
 }
 
+// The part of Eq. 6 that comes from the lambda c1^2 c2^2 c3^2 term of the bulk
+// energy (Eq. 5): with dP/dc_i = 2 lambda c_i c_j^2 c_k^2,
+//   (4 lambda_T / D) sum_{j != i} (dP/dc_i - dP/dc_j) / lambda_j
+//     = kB c1 c2 c3 sum_{j != i} c_k (c_j - c_i) / lambda_j,  kB = 8 lambda lambda_T / D.
+// A uniform branch: lattices with lambda = 0 (Eq. 8) skip it.
+template <typename R, bool LAM = true>
+__device__ __forceinline__ void lambda_term(const Consts<R>& c, R c1, R c2, R& mu1, R& mu2,
+                                            R& mu3) {
+    if (LAM && c.kB != R(0)) {
+        const R c3 = R(1) - c1 - c2;
+        const R t = c.kB * c1 * c2 * c3;
+        mu1 += t * (c3 * (c2 - c1) * c.il2 + c2 * (c3 - c1) * c.il3);
+        mu2 += t * (c3 * (c1 - c2) * c.il1 + c1 * (c3 - c2) * c.il3);
+        mu3 += t * (c2 * (c1 - c3) * c.il1 + c1 * (c2 - c3) * c.il2);
+    }
+}
+
 // Chemical potentials of Eq. 8 at one fluid node from the c values of its
 // 3x3 neighbourhood (row pointers as in Stencil), with the wetting ghosts of
 // Eq. 42 across links into walls and, across a link into a velocity boundary
 // node, the value of the fluid node inside it (Eq. 53).
-template <typename R, bool VEL = true>
+template <typename R, bool VEL = true, bool LAM = true>
 __device__ __forceinline__ void chem_pot(const R* const* c1r, const R* const* c2r,
                                          const uint8_t* const* mr, const R* mt,
                                          const Consts<R>& c, R& mu1, R& mu2, R& mu3) {
@@ -332,6 +354,7 @@ __device__ __forceinline__ void chem_pot(const R* const* c1r, const R* const* c2
     mu1 = c.k12D * (c.lam1 * c1 * (R(1) - c1) * (R(1) - R(2) * c1) - tri) - c.k34D * c.lam1 * l1;
     mu2 = c.k12D * (c.lam2 * c2 * (R(1) - c2) * (R(1) - R(2) * c2) - tri) - c.k34D * c.lam2 * l2;
     mu3 = c.k12D * (c.lam3 * c3 * (R(1) - c3) * (R(1) - R(2) * c3) - tri) - c.k34D * c.lam3 * l3;
+    lambda_term<R, LAM>(c, c1, c2, mu1, mu2, mu3);
 }
 
 // Phase B of the tile kernels: chemical potentials on the mu region.
@@ -535,7 +558,7 @@ __device__ __forceinline__ void pull_f(const Grid& g, const Consts<typename Tr<P
 
 // Chemical potentials of one mu-ring node (mu column mcol, c column
 // mcol + 1) and its solid-neighbour mask.
-template <int P, bool VEL>
+template <int P, unsigned F>
 __device__ __forceinline__ void ring_mu(Ring<P>& sm, const Consts<typename Tr<P>::R>& c,
                                         int y, int y0, int mcol) {
     using R = typename Tr<P>::R;
@@ -555,7 +578,8 @@ __device__ __forceinline__ void ring_mu(Ring<P>& sm, const Consts<typename Tr<P>
 #pragma unroll
     for (int k = 1; k < 9; ++k) {
         const unsigned mn = mr[EY[k] + 1][EX[k]];
-        if (mn) mask |= (VEL && ((c.nee >> mn) & 1u)) ? 1u << (kVelShift + k) : 1u << (k - 1);
+        if (mn)
+            mask |= ((F & kFeatVel) && ((c.nee >> mn) & 1u)) ? 1u << (kVelShift + k) : 1u << (k - 1);
     }
     R mu1 = R(0), mu2 = R(0), mu3 = R(0);
     if (!(mask & kSelfBit)) {
@@ -575,8 +599,10 @@ __device__ __forceinline__ void ring_mu(Ring<P>& sm, const Consts<typename Tr<P>
             mu1 = c.k12D * (c.lam1 * a1 * (R(1) - a1) * (R(1) - R(2) * a1) - tri) - c.k34D * c.lam1 * l1;
             mu2 = c.k12D * (c.lam2 * a2 * (R(1) - a2) * (R(1) - R(2) * a2) - tri) - c.k34D * c.lam2 * l2;
             mu3 = c.k12D * (c.lam3 * a3 * (R(1) - a3) * (R(1) - R(2) * a3) - tri) - c.k34D * c.lam3 * l3;
+            lambda_term<R, (F & kFeatLam) != 0>(c, a1, a2, mu1, mu2, mu3);
         } else {
-            chem_pot<R, VEL>(c1r, c2r, mr, sm.mt, c, mu1, mu2, mu3);
+            chem_pot<R, (F & kFeatVel) != 0, (F & kFeatLam) != 0>(c1r, c2r, mr, sm.mt, c, mu1,
+                                                                  mu2, mu3);
         }
     }
     const int o = mu_slot(y, y0) * RG::MW + mcol;
@@ -592,7 +618,7 @@ __device__ __forceinline__ void ring_mu(Ring<P>& sm, const Consts<typename Tr<P>
 // for a node next to solids, half-way bounce-back into the solid slots
 // (Eq. 44) with the moving-wall term -2 w_k a e_k.u_w / c_s^2 (a = c_i for
 // f^i, rho for g).
-template <int P, bool VEL>
+template <int P, unsigned F>
 __device__ __forceinline__ void node_update(const Grid& g, const Consts<typename Tr<P>::R>& c,
                                             const Stencil<typename Tr<P>::R>& s,
                                             const typename Tr<P>::R* mt, const Nb32& nb,
@@ -603,6 +629,7 @@ __device__ __forceinline__ void node_update(const Grid& g, const Consts<typename
                                             rsrc_t hist, unsigned hstride) {
     using R = typename Tr<P>::R;
     using HT = typename Tr<P>::H;
+    constexpr bool VEL = (F & kFeatVel) != 0;
     const NodeMacro<R> o = node_macro<R, true, VEL>(s, c, gg, mask);
     const R d1x = o.c1 * o.ux - ho[0] * ho[2], d1y = o.c1 * o.uy - ho[0] * ho[3];
     const R d2x = o.c2 * o.ux - ho[1] * ho[2], d2y = o.c2 * o.uy - ho[1] * ho[3];
@@ -735,7 +762,7 @@ __device__ __forceinline__ void node_update(const Grid& g, const Consts<typename
 }
 
 // One strip (tile t) of one lattice.
-template <int P, bool VEL>
+template <int P, unsigned F>
 __device__ __forceinline__ void step_tile(const Grid& g, const Consts<typename Tr<P>::R>& c,
                                           const uint8_t* __restrict__ mat,
                                           const double* __restrict__ mtab, PopBuf srcb,
@@ -763,7 +790,7 @@ __device__ __forceinline__ void step_tile(const Grid& g, const Consts<typename T
             const int r = threadIdx.x / RG::MW;
             const int mcol = threadIdx.x - r * RG::MW;
             const int y = Y + 1 + r;
-            if (y >= y0 - 1) ring_mu<P, VEL>(sm, c, y, y0, mcol);  // prologue: rows below y0-1 lack neighbours
+            if (y >= y0 - 1) ring_mu<P, F>(sm, c, y, y0, mcol);  // prologue: rows below y0-1 lack neighbours
         }
     };
 
@@ -901,8 +928,8 @@ __device__ __forceinline__ void step_tile(const Grid& g, const Consts<typename T
                     cf2[k] = sm.stash[(it - 1) & 1][w - 2][9 + k][lane];
                 }
             }
-            node_update<P, VEL>(g, c, s, sm.mt, nb, idx, live, mask, cf1, cf2, gg, ho, dst, hist,
-                                hstride);
+            node_update<P, F>(g, c, s, sm.mt, nb, idx, live, mask, cf1, cf2, gg, ho, dst, hist,
+                              hstride);
         }
         // phase A of the next iteration (after the last one its loads are
         // all out of range)
@@ -917,9 +944,9 @@ __device__ __forceinline__ void step_tile(const Grid& g, const Consts<typename T
 // binary search.  parity selects which of each lattice's two population
 // buffers is the source in this step.  A lattice's strips are computed by the
 // same code whatever else is in the table, so results do not depend on the
-// batch.  VEL selects the variant that handles velocity boundary nodes
-// (needed when any lattice of the table has them).
-template <int P, bool VEL>
+// batch.  F (kFeatVel, kFeatLam) selects the optional parts that some
+// lattice of the table needs.
+template <int P, unsigned F>
 __global__ __launch_bounds__(kStepThreads)
 __attribute__((amdgpu_waves_per_eu(P == P64 ? 2 : 4)))
 void step_kernel(const unsigned char* __restrict__ descs, int ndesc, int total_tiles, int parity) {
@@ -940,7 +967,7 @@ void step_kernel(const unsigned char* __restrict__ descs, int ndesc, int total_t
     const Grid g = d.g;
     const Consts<typename Tr<P>::R> c = d.c;
     const int sb = (d.cur + parity) & 1;
-    step_tile<P, VEL>(g, c, d.mat, d.mtab, d.buf[sb], d.buf[sb ^ 1], d.hist, L - d.tile_begin, sm);
+    step_tile<P, F>(g, c, d.mat, d.mtab, d.buf[sb], d.buf[sb ^ 1], d.hist, L - d.tile_begin, sm);
 }
 
 // ------------------------------------------------------------------- init
@@ -1142,15 +1169,21 @@ __global__ __launch_bounds__(kThreads) void mass_final_kernel(const double* __re
 template <int P>
 using CT = Consts<typename Tr<P>::R>;
 
+template <int P, unsigned F>
+void step_pf(const void* descs, int ndesc, int total_tiles, int parity, hipStream_t s) {
+    hipLaunchKernelGGL((step_kernel<P, F>), dim3(total_tiles), dim3(kStepThreads), 0, s,
+                       static_cast<const unsigned char*>(descs), ndesc, total_tiles, parity);
+}
+
 template <int P>
-hipError_t step_p(bool vel, const void* descs, int ndesc, int total_tiles, int parity,
+hipError_t step_p(unsigned features, const void* descs, int ndesc, int total_tiles, int parity,
                   hipStream_t s) {
-    if (vel)
-        hipLaunchKernelGGL((step_kernel<P, true>), dim3(total_tiles), dim3(kStepThreads), 0, s,
-                           static_cast<const unsigned char*>(descs), ndesc, total_tiles, parity);
-    else
-        hipLaunchKernelGGL((step_kernel<P, false>), dim3(total_tiles), dim3(kStepThreads), 0, s,
-                           static_cast<const unsigned char*>(descs), ndesc, total_tiles, parity);
+    switch (features & (kFeatVel | kFeatLam)) {
+        case 0: step_pf<P, 0>(descs, ndesc, total_tiles, parity, s); break;
+        case kFeatVel: step_pf<P, kFeatVel>(descs, ndesc, total_tiles, parity, s); break;
+        case kFeatLam: step_pf<P, kFeatLam>(descs, ndesc, total_tiles, parity, s); break;
+        default: step_pf<P, kFeatVel | kFeatLam>(descs, ndesc, total_tiles, parity, s); break;
+    }
     return hipGetLastError();
 }
 
@@ -1158,12 +1191,12 @@ constexpr int kAuxRows = 8;  // tile rows of the init / readout kernels
 
 }  // namespace
 
-hipError_t launch_step(int prec, bool vel, const void* descs, int ndesc, int total_tiles,
-                       int parity, hipStream_t s) {
+hipError_t launch_step(int prec, unsigned features, const void* descs, int ndesc,
+                       int total_tiles, int parity, hipStream_t s) {
     switch (prec) {
-        case P64: return step_p<P64>(vel, descs, ndesc, total_tiles, parity, s);
-        case P32: return step_p<P32>(vel, descs, ndesc, total_tiles, parity, s);
-        case P16: return step_p<P16>(vel, descs, ndesc, total_tiles, parity, s);
+        case P64: return step_p<P64>(features, descs, ndesc, total_tiles, parity, s);
+        case P32: return step_p<P32>(features, descs, ndesc, total_tiles, parity, s);
+        case P16: return step_p<P16>(features, descs, ndesc, total_tiles, parity, s);
         default: return hipErrorInvalidValue;
     }
 }

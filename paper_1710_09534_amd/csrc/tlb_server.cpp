@@ -201,7 +201,8 @@ void release_request(tlb_server* s, Request& r) {
 }
 
 void worker_loop(tlb_server* s) {
-    hipSetDevice(s->device);
+    // every request fails if this thread cannot use the server's device
+    const bool dev_ok = hipSetDevice(s->device) == hipSuccess;
     bool composition_changed = true;
     for (;;) {
         std::vector<std::shared_ptr<Request>> admitted;
@@ -236,7 +237,8 @@ void worker_loop(tlb_server* s) {
             }
         }
         for (auto& rp : admitted) {
-            if (start_request(s, *rp)) {
+            if (!dev_ok) rp->error = "hipSetDevice failed on the server thread";
+            if (dev_ok && start_request(s, *rp)) {
                 std::lock_guard<std::mutex> lk(s->mu);
                 s->running.push_back(rp);
                 composition_changed = true;

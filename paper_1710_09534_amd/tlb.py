@@ -36,7 +36,7 @@ class tlb_fluid(C.Structure):
     _fields_ = [("sigma12", C.c_double), ("sigma13", C.c_double), ("sigma23", C.c_double),
                 ("D", C.c_double), ("M0", C.c_double), ("tau1", C.c_double),
                 ("tau2", C.c_double), ("rho", C.c_double * 3), ("nu", C.c_double * 3),
-                ("gravity", C.c_double * 2)]
+                ("gravity", C.c_double * 2), ("lambda_", C.c_double)]
 
 
 class tlb_material(C.Structure):
@@ -136,6 +136,7 @@ def make_fluid(fl: dict) -> tlb_fluid:
         f.nu[i] = fl["nu"][i]
     g = fl.get("gravity", (0.0, 0.0))
     f.gravity[0], f.gravity[1] = g[0], g[1]
+    f.lambda_ = float(fl.get("lambda", 0.0))
     return f
 
 
