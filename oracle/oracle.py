@@ -11,6 +11,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "tlb_oracle.c")
+_SRC3 = os.path.join(_HERE, "tlb3d_oracle.c")
 _LIB = os.path.join(_HERE, "libtlb_oracle.so")
 
 FIELDS = ("c1", "c2", "c3", "rho", "ux", "uy", "p", "mu1", "mu2", "mu3")
@@ -32,7 +33,7 @@ def build(force: bool = True) -> str:
         return _LIB
     tmp = _LIB + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
-           "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, "-lm"]
+           "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, _SRC3, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, _LIB)
     return _LIB
@@ -64,7 +65,8 @@ def _load():
     with _lock:
         if _lib is not None:
             return _lib
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(
+                os.path.getmtime(_SRC), os.path.getmtime(_SRC3)):
             build()
         lib = C.CDLL(_LIB)
         D = C.POINTER(C.c_double)
@@ -94,6 +96,20 @@ def _load():
             "orc_grad_field": (C.c_int, [vp, D, D, D]),
             "orc_lap_field": (C.c_int, [vp, D, D]),
             "orc_num_threads": (C.c_int, []),
+            "orc3_lattice": (None, [C.POINTER(C.c_int)] * 3 + [D, C.POINTER(C.c_int)]),
+            "orc3_create": (C.c_int, [C.c_int, C.c_int, C.c_int, C.POINTER(_Fluid), C.c_double,
+                                      C.c_int, C.c_int, C.c_int, C.POINTER(C.c_uint8),
+                                      C.POINTER(_Material), C.c_int, C.POINTER(vp)]),
+            "orc3_destroy": (None, [vp]),
+            "orc3_last_error": (C.c_char_p, []),
+            "orc3_init": (C.c_int, [vp, D, D, D, D, D]),
+            "orc3_eval": (C.c_int, [vp]),
+            "orc3_step": (C.c_int, [vp, C.c_int]),
+            "orc3_fields": (C.c_int, [vp, D]),
+            "orc3_populations": (C.c_int, [vp, D]),
+            "orc3_mass": (C.c_int, [vp, D]),
+            "orc3_grad_field": (C.c_int, [vp, D, D, D, D]),
+            "orc3_lap_field": (C.c_int, [vp, D, D]),
             "orc_set_num_threads": (None, [C.c_int]),
         }
         for name, (res, args) in sig.items():
@@ -283,3 +299,100 @@ class Oracle:
     @staticmethod
     def num_threads() -> int:
         return _load().orc_num_threads()
+
+
+# ------------------------------------------------------------------ 3-D
+FIELDS3 = ("c1", "c2", "c3", "rho", "ux", "uy", "uz", "p", "mu1", "mu2", "mu3")
+
+
+def lattice3():
+    lib = _load()
+    ex, ey, ez, opp = ((C.c_int * 19)() for _ in range(4))
+    w = np.zeros(19)
+    lib.orc3_lattice(ex, ey, ez, _dp(w), opp)
+    return np.array(ex[:]), np.array(ey[:]), np.array(ez[:]), w, np.array(opp[:])
+
+
+class Oracle3D:
+    """Three-dimensional FP64 oracle (D3Q19).  ``problem`` holds nx, ny, nz,
+    fluid (with gravity (gx, gy) and "gravity_z"), periodic (px, py, pz),
+    material (uint8 [nz, ny, nx]), mats."""
+
+    def __init__(self, problem: dict, threads: int | None = None):
+        self._lib = _load()
+        if threads:
+            self._lib.orc_set_num_threads(int(threads))
+        self.nx, self.ny, self.nz = int(problem["nx"]), int(problem["ny"]), int(problem["nz"])
+        self.material = np.ascontiguousarray(problem["material"], dtype=np.uint8)
+        assert self.material.shape == (self.nz, self.ny, self.nx)
+        mats = problem.get("mats", [])
+        arr = (_Material * max(1, len(mats)))()
+        for i, m in enumerate(mats):
+            arr[i].theta13_deg = m["theta13"]
+            arr[i].theta23_deg = m["theta23"]
+            wu = m.get("wall_u", (0.0, 0.0))
+            arr[i].wall_u[0], arr[i].wall_u[1] = wu[0], wu[1]
+            arr[i].kind = int(m.get("kind", 0))
+        fl = problem["fluid"]
+        self._fl = _fluid(fl)
+        h = C.c_void_p()
+        px, py, pz = problem.get("periodic", (1, 1, 1))
+        rc = self._lib.orc3_create(self.nx, self.ny, self.nz, C.byref(self._fl),
+                                   float(fl.get("gravity_z", 0.0)), int(px), int(py), int(pz),
+                                   self.material.ctypes.data_as(C.POINTER(C.c_uint8)), arr,
+                                   len(mats), C.byref(h))
+        if rc != 0:
+            raise ValueError("oracle3 create failed (%d): %s"
+                             % (rc, self._lib.orc3_last_error().decode()))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.orc3_destroy(h)
+            self._h = None
+
+    @property
+    def n(self):
+        return self.nx * self.ny * self.nz
+
+    def _arr(self, a):
+        return None if a is None else np.ascontiguousarray(a, dtype=np.float64).reshape(-1)
+
+    def init(self, c1, c2, ux=None, uy=None, uz=None):
+        a = [self._arr(v) for v in (c1, c2, ux, uy, uz)]
+        rc = self._lib.orc3_init(self._h, *[None if v is None else _dp(v) for v in a])
+        assert rc == 0
+
+    def step(self, n: int = 1):
+        if self._lib.orc3_step(self._h, int(n)) != 0:
+            raise RuntimeError(self._lib.orc3_last_error().decode())
+
+    def fields(self) -> dict:
+        out = np.zeros(11 * self.n)
+        assert self._lib.orc3_fields(self._h, _dp(out)) == 0
+        shape = (self.nz, self.ny, self.nx)
+        return {k: out[i * self.n:(i + 1) * self.n].reshape(shape) for i, k in enumerate(FIELDS3)}
+
+    def populations(self) -> np.ndarray:
+        out = np.zeros(57 * self.n)
+        self._lib.orc3_populations(self._h, _dp(out))
+        return out.reshape(57, self.nz, self.ny, self.nx)
+
+    def mass(self) -> np.ndarray:
+        out = np.zeros(3)
+        self._lib.orc3_mass(self._h, _dp(out))
+        return out
+
+    def grad(self, chi):
+        chi = self._arr(chi)
+        g = [np.zeros(self.n) for _ in range(3)]
+        self._lib.orc3_grad_field(self._h, _dp(chi), *[_dp(a) for a in g])
+        shape = (self.nz, self.ny, self.nx)
+        return tuple(a.reshape(shape) for a in g)
+
+    def lap(self, chi):
+        chi = self._arr(chi)
+        out = np.zeros(self.n)
+        self._lib.orc3_lap_field(self._h, _dp(chi), _dp(out))
+        return out.reshape(self.nz, self.ny, self.nx)

@@ -137,6 +137,29 @@ int    orc_lap_field(orc_sim* s, const double* chi, double* lap);
 int    orc_num_threads(void);
 void   orc_set_num_threads(int n);
 
+/* ---- three-dimensional version (tlb3d_oracle.c): D3Q19, walls only ---- */
+typedef struct orc3_sim orc3_sim;
+void   orc3_lattice(int ex[19], int ey[19], int ez[19], double w[19], int opp[19]);
+/* material: [nz][ny][nx], 0 fluid, m >= 1 wall material mats[m-1] (tangential
+ * wall velocity (wall_u[0], wall_u[1], 0)); gravity = (fl->gravity[0],
+ * fl->gravity[1], gravity_z) */
+int    orc3_create(int nx, int ny, int nz, const orc_fluid* fl, double gravity_z,
+                   int px, int py, int pz, const uint8_t* material,
+                   const orc_material* mats, int n_mats, orc3_sim** out);
+void   orc3_destroy(orc3_sim* s);
+const char* orc3_last_error(void);
+int    orc3_init(orc3_sim* s, const double* c1, const double* c2, const double* ux,
+                 const double* uy, const double* uz);
+int    orc3_eval(orc3_sim* s);
+int    orc3_step(orc3_sim* s, int nsteps);
+/* c1, c2, c3, rho, ux, uy, uz, p, mu1, mu2, mu3: 11 x n, boundary nodes 0 */
+int    orc3_fields(orc3_sim* s, double* out);
+/* f1[0..18], f2[0..18], g[0..18]: 57 x n */
+int    orc3_populations(orc3_sim* s, double* out);
+int    orc3_mass(orc3_sim* s, double out[3]);
+int    orc3_grad_field(orc3_sim* s, const double* chi, double* gx, double* gy, double* gz);
+int    orc3_lap_field(orc3_sim* s, const double* chi, double* lap);
+
 #ifdef __cplusplus
 }
 #endif

@@ -419,3 +419,123 @@ def poisson_arrivals(n, rate, seed=7):
         t += -math.log(1.0 - rng.uniform()) / rate
         out.append(t)
     return out
+
+
+# ----------------------------------------------------------------- 3-D inputs
+def coords3(nx, ny, nz):
+    z, y, x = np.meshgrid(np.arange(nz, dtype=np.float64), np.arange(ny, dtype=np.float64),
+                          np.arange(nx, dtype=np.float64), indexing="ij")
+    return x, y, z
+
+
+def tanh_ball(nx, ny, nz, xc, yc, zc, R, D):
+    """Smooth ball indicator 1/2 + 1/2 tanh(2 (R - r) / D)."""
+    x, y, z = coords3(nx, ny, nz)
+    r = np.sqrt((x - xc) ** 2 + (y - yc) ** 2 + (z - zc) ** 2)
+    return 0.5 + 0.5 * np.tanh(2.0 * (R - r) / D)
+
+
+def _problem3(name, nx, ny, nz, fl, periodic, mask, mats, c1, c2, u=None, gravity_z=0.0,
+              steps=0, **extra):
+    solid = mask != 0
+    fl = dict(fl, gravity_z=float(gravity_z))
+    p = {"name": name, "nx": nx, "ny": ny, "nz": nz, "fluid": fl, "periodic": periodic,
+         "material": np.ascontiguousarray(mask, dtype=np.uint8), "mats": mats,
+         "c1": np.ascontiguousarray(np.where(solid, 0.0, c1)),
+         "c2": np.ascontiguousarray(np.where(solid, 0.0, c2)),
+         "ux": None, "uy": None, "uz": None, "steps": steps}
+    if u is not None:
+        for k, a in zip(("ux", "uy", "uz"), u):
+            p[k] = np.ascontiguousarray(np.where(solid, 0.0, a))
+    p.update(extra)
+    return p
+
+
+def random_fields3(nx, ny, nz, seed=11, amp=0.2, geometry="channel", U=0.0,
+                   rho=(1.0, 1.0, 1.0), sigma=(1e-3, 1.3e-3, 1.1e-3),
+                   thetas=((60.0, 100.0), (120.0, 75.0)), gravity=(0.0, 0.0, 0.0), lam=0.0):
+    """Smooth random three-phase mixture in 3-D (low-order Fourier modes) for
+    parity tests.  Geometries: 'channel' (walls in z = 0 and nz-1 moving at
+    -U and +U along x), 'sphere' (a staircase ball in a periodic box), 'box'
+    (walls on every face), 'periodic'."""
+    x, y, z = coords3(nx, ny, nz)
+    rng = Rng(seed)
+
+    def field():
+        acc = np.zeros((nz, ny, nx))
+        for _ in range(4):
+            kx, ky, kz = (int(rng.uniform(1, 3)) for _ in range(3))
+            ph = rng.uniform(0.0, 2.0 * math.pi)
+            acc += np.sin(2 * math.pi * (kx * x / nx + ky * y / ny + kz * z / nz) + ph)
+        return acc / 4.0
+
+    c1 = 0.33 + amp * field()
+    c2 = 0.33 + amp * field()
+    mask = np.zeros((nz, ny, nx), dtype=np.uint8)
+    if geometry == "channel":
+        mask[0], mask[nz - 1] = 1, 2
+        mats = [material(*thetas[0], wall_u=(-U, 0.0)), material(*thetas[1], wall_u=(U, 0.0))]
+        periodic = (1, 1, 0)
+    elif geometry == "sphere":
+        r = np.sqrt((x - nx / 2) ** 2 + (y - ny / 2) ** 2 + (z - nz / 2) ** 2)
+        mask[r <= min(nx, ny, nz) / 5.0] = 1
+        mats = [material(*thetas[0])]
+        periodic = (1, 1, 1)
+    elif geometry == "box":
+        mask[0], mask[nz - 1] = 1, 1
+        mask[:, 0], mask[:, ny - 1] = 2, 2
+        mask[:, :, 0], mask[:, :, nx - 1] = 2, 2
+        mats = [material(*thetas[0]), material(*thetas[1])]
+        periodic = (0, 0, 0)
+    else:
+        mats = []
+        periodic = (1, 1, 1)
+    ux = 0.01 * np.sin(2 * math.pi * y / ny)
+    uy = 0.01 * np.cos(2 * math.pi * z / nz)
+    uz = 0.01 * np.sin(2 * math.pi * x / nx)
+    fl = fluid(sigma=sigma, D=4.0, M0=1e-4, tau=(0.8, 0.9), rho=rho, nu=(0.1, 0.05, 0.15),
+               gravity=gravity[:2], lam=lam)
+    return _problem3("random3_%s_%dx%dx%d_s%d" % (geometry, nx, ny, nz, seed), nx, ny, nz, fl,
+                     periodic, mask, mats, c1, c2, u=(ux, uy, uz), gravity_z=gravity[2])
+
+
+def sessile3d(nx=128, ny=128, nz=64, R_core=16.0, R_shell=32.0, theta13=60.0, theta23=90.0,
+              sigma=1e-3, steps=2000):
+    """Compound drop (phase-1 core, phase-2 shell) resting on a wetting wall
+    in the plane z = 0 of a box periodic in x and y, neutral wall on top; the
+    3-D analogue of the sessile drops of Sec. III.A-B."""
+    D = 4.0
+    core = tanh_ball(nx, ny, nz, nx / 2, ny / 2, 0.5, R_core, D)
+    shell = tanh_ball(nx, ny, nz, nx / 2, ny / 2, 0.5, R_shell, D) - core
+    mask = np.zeros((nz, ny, nx), dtype=np.uint8)
+    mask[0], mask[nz - 1] = 1, 2
+    mats = [material(theta13, theta23), material(90.0, 90.0)]
+    fl = fluid(sigma=(sigma, sigma, sigma), D=D, M0=0.1 * sigma, tau=(0.8, 0.8),
+               rho=(1, 1, 1), nu=(0.1, 0.1, 0.1))
+    return _problem3("sessile3d_%dx%dx%d" % (nx, ny, nz), nx, ny, nz, fl, (1, 1, 0), mask, mats,
+                     core, np.clip(shell, 0.0, None), steps=steps)
+
+
+def sphere_impact3d(nx=192, ny=192, nz=256, R_sphere=40.0, R_shell=32.0, R_core=16.0,
+                    We=10.0, theta=90.0, sigma=5e-3):
+    """3-D analogue of the cylinder impact of Sec. III.E: a compound drop
+    (phase-1 core, phase-2 shell, densities 10/10/1) moving down onto a
+    staircase sphere in a periodic box, touching it at t = 0."""
+    D = 4.0
+    xs, ys, zs = nx / 2.0, ny / 2.0, nz * 0.4
+    zd = zs + R_sphere + R_shell
+    core = tanh_ball(nx, ny, nz, xs, ys, zd, R_core, D)
+    shell = tanh_ball(nx, ny, nz, xs, ys, zd, R_shell, D) - core
+    x, y, z = coords3(nx, ny, nz)
+    mask = np.zeros((nz, ny, nx), dtype=np.uint8)
+    mask[(x - xs) ** 2 + (y - ys) ** 2 + (z - zs) ** 2 <= R_sphere ** 2] = 1
+    rho_bar, xi = 10.0, 2.0 * R_shell
+    U = math.sqrt(We * sigma / (rho_bar * xi))
+    cs = np.clip(shell, 0.0, None)
+    uz = -U * (core + cs)
+    fl = fluid(sigma=(sigma, sigma, sigma), D=D, M0=0.1 * sigma, tau=(0.8, 0.8),
+               rho=(10, 10, 1), nu=(0.1, 0.1, 0.1))
+    z0 = np.zeros_like(uz)
+    return _problem3("sphere_impact3d_%dx%dx%d_We%g" % (nx, ny, nz, We), nx, ny, nz, fl,
+                     (1, 1, 1), mask, [material(theta, theta)], core, cs, u=(z0, z0, uz),
+                     U=U, We=We)
