@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtlb.so")
-SOURCES = ["tlb_kernels.hip", "tlb_host.cpp", "tlb_server.cpp"]
+SOURCES = ["tlb_kernels.hip", "tlb_host.cpp", "tlb_server.cpp", "tlb3d_kernels.hip", "tlb3d_host.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed-FP32 instructions are disabled on purpose.

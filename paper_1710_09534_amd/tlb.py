@@ -107,6 +107,21 @@ _SIGS = {
     "tlb_server_destroy": (None, [_vp]),
     "tlb_last_error": (C.c_char_p, [_vp]),
     "tlb_destroy": (None, [_vp]),
+    # three-dimensional (D3Q19) step, include/tlb3d.h
+    "tlb3_workspace_bytes": (C.c_size_t, [C.c_int, C.c_int, C.c_int, C.c_int]),
+    "tlb3_create": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(tlb_fluid),
+                              C.c_double, _vp, C.c_size_t, _vp, C.POINTER(_vp)]),
+    "tlb3_set_geometry": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_uint8),
+                                    C.POINTER(tlb_material), C.c_int, _D]),
+    "tlb3_init_fields": (C.c_int, [_vp, _D, _D, _D, _D, _D]),
+    "tlb3_step": (C.c_int, [_vp, C.c_int64]),
+    "tlb3_set_check_interval": (C.c_int, [_vp, C.c_int64]),
+    "tlb3_read_fields": (C.c_int, [_vp, C.c_uint32, _D]),
+    "tlb3_read_populations": (C.c_int, [_vp, _D]),
+    "tlb3_mass": (C.c_int, [_vp, _D]),
+    "tlb3_time_steps": (C.c_int, [_vp, C.c_int64, _D]),
+    "tlb3_last_error": (C.c_char_p, [_vp]),
+    "tlb3_destroy": (None, [_vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _fn = getattr(lib, _name)
@@ -308,6 +323,116 @@ class Batch:
         if h is not None and h.value:
             _lib.tlb_batch_destroy(h)
             self.h = None
+
+
+FIELDS3 = ("c1", "c2", "c3", "rho", "ux", "uy", "uz", "p", "mu1", "mu2", "mu3")
+
+
+class Solver3D:
+    """One three-dimensional (D3Q19) lattice on the current HIP device:
+    owns a torch workspace and the C context (tlb3_*)."""
+
+    def __init__(self, nx: int, ny: int, nz: int, fluid: dict, precision="fp64",
+                 device="cuda:0"):
+        import torch
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        nbytes = int(lib.tlb3_workspace_bytes(self.nx, self.ny, self.nz, self.precision))
+        if nbytes == 0:
+            raise TlbError(TLB_EINVAL, "unsupported size or precision for the 3-D step")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.stream = torch.cuda.current_stream(device)
+        self._fluid = make_fluid(fluid)
+        h = _vp()
+        st = lib.tlb3_create(self.nx, self.ny, self.nz, self.precision, C.byref(self._fluid),
+                             float(fluid.get("gravity_z", 0.0)), _vp(self.workspace.data_ptr()),
+                             nbytes, _vp(self.stream.cuda_stream), C.byref(h))
+        if st != TLB_OK:
+            raise TlbError(st, lib.tlb3_last_error(None).decode())
+        self.ctx = h
+
+    def __del__(self):
+        self.destroy()
+
+    def destroy(self, _lib=lib):
+        ctx = getattr(self, "ctx", None)
+        if ctx is not None and ctx.value:
+            _lib.tlb3_destroy(ctx)
+        self.ctx = None
+
+    @property
+    def n(self):
+        return self.nx * self.ny * self.nz
+
+    def _check(self, st):
+        if st != TLB_OK:
+            raise TlbError(st, lib.tlb3_last_error(self.ctx).decode())
+
+    def _f(self, a):
+        if a is None:
+            return None
+        a = np.ascontiguousarray(a, dtype=np.float64).reshape(-1)
+        if a.size != self.n:
+            raise ValueError("field size mismatch")
+        return a
+
+    def set_geometry(self, material, mats, periodic=(1, 1, 1)):
+        material = np.ascontiguousarray(material, dtype=np.uint8)
+        if material.shape != (self.nz, self.ny, self.nx):
+            raise ValueError("material shape mismatch")
+        arr = make_materials(mats)
+        th12 = np.zeros(max(1, len(mats)))
+        self._check(lib.tlb3_set_geometry(self.ctx, int(periodic[0]), int(periodic[1]),
+                                          int(periodic[2]),
+                                          material.ctypes.data_as(C.POINTER(C.c_uint8)), arr,
+                                          len(mats), _dp(th12)))
+        return th12[:len(mats)]
+
+    def init_fields(self, c1, c2, ux=None, uy=None, uz=None):
+        a = [self._f(v) for v in (c1, c2, ux, uy, uz)]
+        self._check(lib.tlb3_init_fields(self.ctx, *[_dp(v) for v in a]))
+
+    def step(self, n: int = 1):
+        self._check(lib.tlb3_step(self.ctx, int(n)))
+
+    def set_check_interval(self, n: int):
+        self._check(lib.tlb3_set_check_interval(self.ctx, int(n)))
+
+    def read_fields(self, names=FIELDS3) -> dict:
+        mask = 0
+        for nm in names:
+            mask |= 1 << FIELDS3.index(nm)
+        order = [nm for nm in FIELDS3 if mask & (1 << FIELDS3.index(nm))]
+        out = np.zeros(len(order) * self.n)
+        self._check(lib.tlb3_read_fields(self.ctx, mask, _dp(out)))
+        shape = (self.nz, self.ny, self.nx)
+        return {nm: out[i * self.n:(i + 1) * self.n].reshape(shape) for i, nm in enumerate(order)}
+
+    def read_populations(self) -> np.ndarray:
+        out = np.zeros(57 * self.n)
+        self._check(lib.tlb3_read_populations(self.ctx, _dp(out)))
+        return out.reshape(57, self.nz, self.ny, self.nx)
+
+    def mass(self) -> np.ndarray:
+        out = np.zeros(3)
+        self._check(lib.tlb3_mass(self.ctx, _dp(out)))
+        return out
+
+    def time_steps(self, n: int) -> float:
+        ms = C.c_double()
+        self._check(lib.tlb3_time_steps(self.ctx, int(n), C.byref(ms)))
+        return ms.value
+
+
+def from_problem3(problem: dict, precision="fp64", device="cuda:0", init=True) -> Solver3D:
+    """Creates a 3-D solver for a problem dict of ``workloads`` (``*3d``,
+    ``random_fields3``) and initialises it."""
+    s = Solver3D(problem["nx"], problem["ny"], problem["nz"], problem["fluid"], precision, device)
+    s.set_geometry(problem["material"], problem["mats"], problem.get("periodic", (1, 1, 1)))
+    if init:
+        s.init_fields(problem["c1"], problem["c2"], problem.get("ux"), problem.get("uy"),
+                      problem.get("uz"))
+    return s
 
 
 def from_problem(problem: dict, precision="fp64", device="cuda:0", init=True) -> Solver:

@@ -1,5 +1,5 @@
 """Host-side checks of the C-ABI library that need no GPU: it loads, exports
-every symbol include/tlb.h declares, sizes workspaces, and rejects invalid
+every symbol include/*.h declares, sizes workspaces, and rejects invalid
 input before touching the device."""
 import ctypes as C
 import os
@@ -9,14 +9,16 @@ import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "tlb.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("tlb.h", "tlb3d.h")]
 LIB = os.path.join(ROOT, "paper_1710_09534_amd", "libtlb.so")
 
 
 def declared_symbols():
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(tlb_[a-z0-9_]+)\s*\(", src)))
+    out = set()
+    for h in HEADERS:
+        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        out |= set(re.findall(r"\b(tlb3?_[a-z0-9_]+)\s*\(", src))
+    return sorted(out)
 
 
 @pytest.fixture(scope="module")
@@ -29,7 +31,7 @@ def lib():
 
 def test_exports_every_declared_symbol(lib):
     syms = declared_symbols()
-    assert len(syms) >= 15
+    assert len(syms) >= 45 and any(s.startswith("tlb3_") for s in syms)
     for s in syms:
         assert hasattr(lib, s), s
 
@@ -105,3 +107,29 @@ def test_null_context_calls_fail_cleanly():
     assert tlb.lib.tlb_mass(None, tlb._dp(out)) == tlb.TLB_EINVAL
     assert tlb.lib.tlb_step_count(None) == -1
     tlb.lib.tlb_destroy(None)
+
+
+def test_workspace_sizes_3d():
+    from paper_1710_09534_amd import tlb
+    n = 64 * 48 * 40
+    b64 = int(tlb.lib.tlb3_workspace_bytes(64, 48, 40, tlb.TLB_FP64))
+    b32 = int(tlb.lib.tlb3_workspace_bytes(64, 48, 40, tlb.TLB_FP32))
+    # two lattices of 57 planes + 5 history + 2 c + 3 mu planes
+    assert b64 >= n * (2 * 57 + 10) * 8
+    assert b32 >= n * (2 * 57 + 10) * 4
+    assert int(tlb.lib.tlb3_workspace_bytes(64, 48, 40, tlb.TLB_FP16DEV)) == 0
+    assert int(tlb.lib.tlb3_workspace_bytes(64, 2, 40, tlb.TLB_FP64)) == 0
+
+
+def test_create3_rejections():
+    from paper_1710_09534_amd import tlb
+    fl = tlb.make_fluid(_fl())
+    h = C.c_void_p()
+    ws = (C.c_uint8 * 512)()
+    st = tlb.lib.tlb3_create(16, 16, 16, tlb.TLB_FP16DEV, C.byref(fl), 0.0, C.cast(ws, C.c_void_p),
+                             512, None, C.byref(h))
+    assert st == tlb.TLB_EINVAL
+    st = tlb.lib.tlb3_create(16, 16, 16, tlb.TLB_FP64, C.byref(fl), 0.0, C.cast(ws, C.c_void_p),
+                             512, None, C.byref(h))
+    assert st in (tlb.TLB_EINVAL, tlb.TLB_ENOMEM)
+    assert not h.value
