@@ -2,7 +2,7 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32]
                     [--workload cylinder_impact] [--only] [--no-cpu]
-                    [--no-serving] [--no-sweep] [--copy-calibration MIB]
+                    [--no-serving] [--no-sweep] [--no-3d] [--copy-calibration MIB]
 
 Workload: the compound-drop / cylinder-impact lattice, 1024 x 2048 nodes,
 staircase cylinder of radius 128 (We = 10, theta = 90 deg), FP32
@@ -116,6 +116,33 @@ def bw_sweep_leg(tlb, torch, sizes=((1024, 2048), (2048, 2048), (4096, 4096)), s
                         "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)})
             print("# bw sweep %s %s %.4f ms %.0f MLUPS %.0f GB/s" %
                   (out[-1]["size"], prec, kms, out[-1]["mlups"], gbs), file=sys.stderr, flush=True)
+    return out
+
+
+def leg_3d(tlb, torch, steps=100):
+    """The three-dimensional (D3Q19) step on the sphere-impact lattice
+    (192 x 192 x 256, compound drop onto a staircase sphere): device time per
+    step from HIP events, MLUPS and the algorithmic bandwidth (populations and
+    history read and written once: 2 * (57 + 5) * s bytes per fluid node, plus
+    1 byte of material per node)."""
+    from paper_1710_09534_amd import workloads as W
+    prob = W.sphere_impact3d()
+    n = prob["nx"] * prob["ny"] * prob["nz"]
+    fluid = int((prob["material"] == 0).sum())
+    out = {"workload": "sphere_impact3d %dx%dx%d" % (prob["nx"], prob["ny"], prob["nz"])}
+    for prec, s in (("fp32", 4), ("fp64", 8)):
+        sol = tlb.from_problem3(prob, prec)
+        sol.set_check_interval(0)
+        sol.time_steps(5)
+        kms = sol.time_steps(steps)
+        del sol
+        torch.cuda.synchronize()
+        alg = fluid * 2 * (57 + 5) * s + n
+        gbs = alg / (kms * 1e-3) / 1e9
+        out[prec] = {"ms_per_step": round(kms, 4), "mlups": round(n / kms / 1e3, 1),
+                     "algorithmic_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+        print("# 3-D %s: %.4f ms/step %.0f MLUPS %.0f GB/s" % (prec, kms, n / kms / 1e3, gbs),
+              file=sys.stderr, flush=True)
     return out
 
 
@@ -250,6 +277,7 @@ def main():
     ap.add_argument("--only", action="store_true", help="time the headline precision only")
     ap.add_argument("--no-serving", action="store_true", help="skip the batching and serving legs")
     ap.add_argument("--no-sweep", action="store_true", help="skip the bandwidth sweep leg")
+    ap.add_argument("--no-3d", action="store_true", help="skip the three-dimensional leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB, 10 times (counter scale)")
     args = ap.parse_args()
@@ -329,6 +357,8 @@ def main():
     }
     if not (args.only or args.no_sweep):
         out["bw_sweep"] = bw_sweep_leg(tlb, torch)
+    if not (args.only or args.no_3d):
+        out["d3q19"] = leg_3d(tlb, torch)
     if not (args.only or args.no_serving):
         out["batching"] = batching_leg(tlb, torch)
         print("# batching: %s" % out["batching"], file=sys.stderr, flush=True)
