@@ -2,7 +2,8 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32]
                     [--workload cylinder_impact] [--only] [--no-cpu]
-                    [--no-serving] [--no-sweep] [--no-3d] [--copy-calibration MIB]
+                    [--no-serving] [--no-sweep] [--no-3d] [--serving-full]
+                    [--copy-calibration MIB]
 
 Workload: the compound-drop / cylinder-impact lattice, 1024 x 2048 nodes,
 staircase cylinder of radius 128 (We = 10, theta = 90 deg), FP32
@@ -180,18 +181,22 @@ def batching_leg(tlb, torch, precision="fp32", n_lattices=256, size=64, steps=20
 
 
 def serving_leg(tlb, torch, precision="fp32", n_requests=120, steps=(1000, 4000),
-                arena_gb=40.0, slots=64, quantum=250):
+                arena_gb=40.0, slots=64, quantum=250, calibrate_sequential=False):
     """A seeded stream of independent drop solves (sizes 64^2..1024^2
     weighted 0.40/0.30/0.15/0.10/0.05, single/binary/compound drops, random
     angles and surface tensions) served with continuous batching under an
     HBM arena, at Poisson loads of 0.7x and 1.2x the measured capacity; and
-    the same stream solved one request at a time by the plain FP64 path."""
+    the same stream solved one request at a time by the plain FP64 path
+    (FIFO, one request on the GPU at a time).  With calibrate_sequential the
+    FP64 service time of each request is its size class's measured set-up
+    time plus its steps times the class's measured time per step, instead
+    of running every request."""
     from paper_1710_09534_amd import workloads as W
     stream = W.serving_stream(n_requests, seed=2026, steps=steps)
     probs = [f() for (_, _, f) in stream]
     work = sum(p["nx"] * p["ny"] * p["steps"] for p in probs)
 
-    def run(arrivals):
+    def run(arrivals, tag):
         srv = tlb.Server(int(arena_gb * (1 << 30)), max_slots=slots, precision=precision,
                          quantum=quantum)
         t0 = time.perf_counter()
@@ -201,16 +206,22 @@ def serving_leg(tlb, torch, precision="fp32", n_requests=120, steps=(1000, 4000)
             if ta > now:
                 time.sleep(ta - now)
             ids.append(srv.submit(p, p["steps"], fields=0))
-        for i in ids:
-            srv.wait(i, 600.0)
+        last = time.perf_counter()
+        for k, i in enumerate(ids):
+            srv.wait(i, 1800.0)
+            if time.perf_counter() - last > 30.0:
+                last = time.perf_counter()
+                print("# serving %s: %d/%d done at %.0f s" % (tag, k + 1, len(ids), last - t0),
+                      file=sys.stderr, flush=True)
         makespan = time.perf_counter() - t0
         lat = np.array([srv.latency(i) for i in ids])
         st = srv.stats()
         srv.close()
+        print("# serving %s: makespan %.1f s" % (tag, makespan), file=sys.stderr, flush=True)
         return makespan, lat, st
 
     # capacity: everything submitted at once
-    makespan, lat, st = run([0.0] * len(probs))
+    makespan, lat, st = run([0.0] * len(probs), "capacity")
     cap = len(probs) / makespan
     out = {"requests": len(probs), "precision": precision, "steps_range": list(steps),
            "arena_gb": arena_gb, "slots": slots, "quantum": quantum,
@@ -218,22 +229,41 @@ def serving_leg(tlb, torch, precision="fp32", n_requests=120, steps=(1000, 4000)
            "closed_batch_mlups": round(work / makespan / 1e6, 1)}
     for tag, load in (("load_0.7", 0.7), ("load_1.2", 1.2)):
         arr = W.poisson_arrivals(len(probs), load * cap, seed=7)
-        makespan, lat, st = run(arr)
+        makespan, lat, st = run(arr, tag)
         out[tag] = {"p50_s": round(float(np.percentile(lat, 50)), 4),
                     "p99_s": round(float(np.percentile(lat, 99)), 4),
                     "aggregate_mlups": round(work / makespan / 1e6, 1),
                     "failed": int(st["failed"])}
-    # one request at a time, plain FP64, same arrivals (FIFO single server)
-    service = []
-    for p in probs:
+
+    def solo(p, nsteps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         s = tlb.from_problem(p, "fp64")
         s.set_check_interval(0)
-        s.step(p["steps"])
+        if nsteps:
+            s.step(nsteps)
         s.mass()
-        service.append(time.perf_counter() - t0)
+        dt = time.perf_counter() - t0
         del s
+        return dt
+
+    if calibrate_sequential:
+        # per size class: set-up (create, init, readout of the mass) and time
+        # per step of the plain FP64 path on that size alone
+        cal = {}
+        for p in probs:
+            n = p["nx"]
+            if n in cal:
+                continue
+            t_set = solo(p, 0)
+            t_run = solo(p, 400) - t_set
+            cal[n] = (t_set, t_run / 400.0)
+        service = [cal[p["nx"]][0] + cal[p["nx"]][1] * p["steps"] for p in probs]
+        out["sequential_fp64_model"] = {str(k): {"setup_s": round(v[0], 4),
+                                                 "ms_per_step": round(1e3 * v[1], 4)}
+                                        for k, v in sorted(cal.items())}
+    else:
+        service = [solo(p, p["steps"]) for p in probs]
     for tag, load in (("load_0.7", 0.7), ("load_1.2", 1.2)):
         arr = W.poisson_arrivals(len(probs), load * cap, seed=7)
         fin, tts = 0.0, []
@@ -278,6 +308,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the batching and serving legs")
     ap.add_argument("--no-sweep", action="store_true", help="skip the bandwidth sweep leg")
     ap.add_argument("--no-3d", action="store_true", help="skip the three-dimensional leg")
+    ap.add_argument("--serving-full", action="store_true",
+                    help="also serve the full 1000-request stream (several minutes)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB, 10 times (counter scale)")
     args = ap.parse_args()
@@ -359,6 +391,13 @@ def main():
         out["bw_sweep"] = bw_sweep_leg(tlb, torch)
     if not (args.only or args.no_3d):
         out["d3q19"] = leg_3d(tlb, torch)
+    if args.serving_full:
+        # the whole seeded stream of the serving workload: 1000 requests of
+        # 1000-20000 steps under a 200 GB arena (minutes of GPU time)
+        out["serving_full"] = serving_leg(tlb, torch, n_requests=1000, steps=(1000, 20000),
+                                          arena_gb=200.0, slots=128, quantum=500,
+                                          calibrate_sequential=True)
+        print("# serving (full stream): %s" % out["serving_full"], file=sys.stderr, flush=True)
     if not (args.only or args.no_serving):
         out["batching"] = batching_leg(tlb, torch)
         print("# batching: %s" % out["batching"], file=sys.stderr, flush=True)

@@ -145,6 +145,17 @@ void fill_consts(Consts<R>& k, const tlb_ctx* c) {
     k.nee = 0u;
 }
 
+// Default strip height: 64 rows, or the tallest of 48, 32, 24, 16 that still
+// gives the lattice one strip per compute unit (a lone small lattice
+// otherwise runs as a few workgroups each marching 64 rows in sequence).
+int default_rows(int nx, int ny) {
+    const int tx = (nx + kTileX - 1) / kTileX;
+    static const int cand[] = {64, 48, 32, 24};
+    for (int rows : cand)
+        if (tx * ((ny + rows - 1) / rows) >= 256) return rows;
+    return 16;
+}
+
 void set_grid(tlb_ctx* c, int rows) {
     c->grid.nx = c->nx;
     c->grid.ny = c->ny;
@@ -276,7 +287,7 @@ tlb_status tlb_create(int nx, int ny, tlb_precision p, const tlb_fluid* fl, void
     c->eta[1] = c->M[1] / (cs2 * (fl->tau2 - 0.5));
     fill_consts(c->c64, c);
     fill_consts(c->c32, c);
-    set_grid(c, 64);
+    set_grid(c, default_rows(nx, ny));
     if (hipHostMalloc(reinterpret_cast<void**>(&c->health), 4 * sizeof(double)) != hipSuccess) {
         delete c;
         return fail(nullptr, TLB_ENOMEM, "pinned health word");

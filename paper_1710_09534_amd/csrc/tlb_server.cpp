@@ -156,6 +156,9 @@ bool start_request(tlb_server* s, Request& r) {
         st = tlb_init_fields(r.ctx, r.c1.data(), r.c2.data(), r.ux.empty() ? nullptr : r.ux.data(),
                              r.uy.empty() ? nullptr : r.uy.data());
     if (st == TLB_OK) st = tlb_set_check_interval(r.ctx, 0);
+    // in a batch every step lasts as long as its tallest strip, so shorter
+    // strips for small lattices would only add halo work
+    if (st == TLB_OK) st = tlb_set_tile_rows(r.ctx, 64);
     if (st != TLB_OK) {
         r.error = tlb_last_error(r.ctx);
         return false;
