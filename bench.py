@@ -2,7 +2,7 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32]
                     [--workload cylinder_impact] [--only] [--no-cpu]
-                    [--no-serving] [--no-sweep] [--no-3d] [--serving-full]
+                    [--no-serving] [--no-sweep] [--no-3d] [--only-3d] [--serving-full]
                     [--copy-calibration MIB]
 
 Workload: the compound-drop / cylinder-impact lattice, 1024 x 2048 nodes,
@@ -308,6 +308,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the batching and serving legs")
     ap.add_argument("--no-sweep", action="store_true", help="skip the bandwidth sweep leg")
     ap.add_argument("--no-3d", action="store_true", help="skip the three-dimensional leg")
+    ap.add_argument("--only-3d", action="store_true",
+                    help="run only the three-dimensional leg (--steps steps per precision)")
     ap.add_argument("--serving-full", action="store_true",
                     help="also serve the full 1000-request stream (several minutes)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -338,6 +340,10 @@ def main():
         return
     from paper_1710_09534_amd import tlb
 
+    if args.only_3d:
+        # diagnostic mode (profiling): the three-dimensional leg alone
+        print(json.dumps({"d3q19": leg_3d(tlb, torch, steps=args.steps)}), flush=True)
+        return
     problem = make_problem(args.workload, args.nx, args.ny)
     n = problem["nx"] * problem["ny"]
     fluid = int((problem["material"] == 0).sum())
