@@ -122,13 +122,14 @@ def test_cylinder_impact_small(tlb):
 
 
 @pytest.mark.parametrize("factory,steps", [
-    (lambda: W.binary_drops(seed=0), 20),
-    (lambda: W.compound_shear(seed=0), 10),
-    (lambda: W.cylinder_impact(We=100, theta=150), 3),
-])
+    (lambda: W.binary_drops(seed=0), 1000),
+    (lambda: W.compound_shear(seed=0), 1000),
+    (lambda: W.cylinder_impact(We=100, theta=150), 100),
+], ids=["binary_drops_256x128", "compound_shear_512x256", "cylinder_impact_1024x2048"])
 def test_full_size_workloads(tlb, factory, steps):
-    """The 256x128, 512x256 and 1024x2048 workloads at full size, few steps,
-    in the tile shape the benchmark uses."""
+    """The 256x128 and 512x256 workloads at full size for 1000 steps, the
+    1024x2048 one for 100 steps, in the launch configuration the benchmark
+    uses (64-row strips on the large lattice)."""
     p = factory()
     g, o = run_pair(tlb, p, steps)
     assert_parity(g, o, pops=False)
