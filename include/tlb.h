@@ -108,7 +108,8 @@ enum {
 typedef struct tlb_ctx tlb_ctx;
 
 /* Device workspace needed for an nx x ny lattice at precision p (bytes).
- * Returns 0 for nx or ny < 3. */
+ * Returns 0 for nx or ny < 3, an unknown precision, or a lattice beyond the
+ * size limit of tlb_create. */
 size_t tlb_workspace_bytes(int nx, int ny, tlb_precision p);
 
 /* Create a context on a caller-owned device workspace (at least
@@ -117,8 +118,10 @@ size_t tlb_workspace_bytes(int nx, int ny, tlb_precision p);
  * parameters (Eqs. 7, 9, 18): lambda_i > 0, lambda >= 0, lambda_i >
  * lambda_T/2 when lambda = 0 (the range stated for that energy), tau_i > 1/2,
  * D > 0, M0 > 0, rho_i > 0, nu_i > 0 (else TLB_EPARAM).
- * Each family of 9 population planes must stay below 2 GiB (FP64: about
- * 29.8 M nodes, e.g. 5400 x 5400; else TLB_EINVAL).
+ * Each family of 9 population planes and the history must stay below 2 GiB,
+ * counted with rows padded to a multiple of 64 nodes: at most about 29.8 M
+ * nodes in FP64 (e.g. 5400 x 5400), 59.6 M in FP32, 119.3 M in FP16-dev;
+ * else TLB_EINVAL.
  * The library owns *out until tlb_destroy. */
 tlb_status tlb_create(int nx, int ny, tlb_precision p, const tlb_fluid* fl,
                       void* dev_workspace, size_t ws_bytes, void* hip_stream,

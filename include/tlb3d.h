@@ -43,13 +43,17 @@ enum {
 typedef struct tlb3_ctx tlb3_ctx;
 
 /* Device workspace for an nx x ny x nz lattice (bytes); 0 for a dimension
- * < 3 or an unsupported precision. */
+ * < 3, nz > 65535, an unsupported precision, or a lattice beyond the size
+ * limit of tlb3_create. */
 size_t tlb3_workspace_bytes(int nx, int ny, int nz, tlb_precision p);
 
 /* Create a context on a caller-owned device workspace (>= tlb3_workspace_bytes,
  * 256-byte aligned, alive until tlb3_destroy) and a HIP stream (NULL =
  * default).  fl: as in tlb_create (same validation); gravity = (fl->gravity[0],
- * fl->gravity[1], gravity_z). */
+ * fl->gravity[1], gravity_z).  Each family of 19 population planes must stay
+ * below 2 GiB, counted with rows padded to a multiple of 64 nodes: at most
+ * about 14.1 M nodes in FP64 (e.g. 192 x 240 x 300), 28.2 M in FP32; a larger
+ * lattice, or nz > 65535, is TLB_EINVAL. */
 tlb_status tlb3_create(int nx, int ny, int nz, tlb_precision p, const tlb_fluid* fl,
                        double gravity_z, void* dev_workspace, size_t ws_bytes, void* hip_stream,
                        tlb3_ctx** out);

@@ -4,6 +4,7 @@
 // context's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -24,6 +25,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct Layout3 {
     int pitch;
     size_t npad, n;
+    size_t stage_doubles;
     size_t off_pop[2], off_hist, off_cf, off_muf, off_mat, off_mtab, off_stage, off_part,
         off_result, total;
 };
@@ -45,7 +47,10 @@ Layout3 make_layout3(int nx, int ny, int nz, int prec) {
     L.off_mat = o; o += align_up(L.npad, kAlign);
     L.off_mtab = o; o += align_up(kMatStride * (kMaxMaterials + 1) * sizeof(double), kAlign);
     // staging: inputs of init (5 fields), readout (11), one population family (19)
-    L.off_stage = o; o += align_up(19 * L.n * sizeof(double), kAlign);
+    // staging: the 5 input fields of init; readout and population copies pass
+    // through it in bands of z-planes (at least one plane of 19 populations)
+    L.stage_doubles = std::max(5 * L.n, size_t(kQ) * nx * ny);
+    L.off_stage = o; o += align_up(L.stage_doubles * sizeof(double), kAlign);
     L.off_part = o; o += align_up(kReduceBlocks * 3 * sizeof(double), kAlign);
     L.off_result = o; o += kAlign;
     L.total = o;
@@ -178,9 +183,16 @@ tlb_status step_impl(tlb3_ctx* c, int64_t nsteps, bool checks) {
 
 extern "C" {
 
+// the fused step kernel addresses each family of 19 planes as one buffer
+// resource with 32-bit sizes and offsets
+static bool fits_offsets3(const Layout3& L, int p) {
+    return size_t(kQ) * L.npad * (p == 0 ? 8 : 4) < (size_t(1) << 31);
+}
+
 size_t tlb3_workspace_bytes(int nx, int ny, int nz, tlb_precision p) {
-    if (nx < 3 || ny < 3 || nz < 3 || (p != TLB_FP64 && p != TLB_FP32)) return 0;
-    return make_layout3(nx, ny, nz, int(p)).total;
+    if (nx < 3 || ny < 3 || nz < 3 || nz > 65535 || (p != TLB_FP64 && p != TLB_FP32)) return 0;
+    const Layout3 L = make_layout3(nx, ny, nz, int(p));
+    return fits_offsets3(L, int(p)) ? L.total : 0;
 }
 
 tlb_status tlb3_create(int nx, int ny, int nz, tlb_precision p, const tlb_fluid* fl,
@@ -196,6 +208,8 @@ tlb_status tlb3_create(int nx, int ny, int nz, tlb_precision p, const tlb_fluid*
     if (reinterpret_cast<uintptr_t>(dev_workspace) % kAlign)
         return fail(nullptr, TLB_EINVAL, "workspace must be 256-byte aligned");
     const Layout3 L = make_layout3(nx, ny, nz, int(p));
+    if (!fits_offsets3(L, int(p)))
+        return fail(nullptr, TLB_EINVAL, "lattice too large: a family of 19 planes must stay below 2 GiB");
     if (ws_bytes < L.total) return fail(nullptr, TLB_ENOMEM, "workspace too small");
     double lam[3] = {fl->sigma12 + fl->sigma13 - fl->sigma23, fl->sigma12 + fl->sigma23 - fl->sigma13,
                      fl->sigma13 + fl->sigma23 - fl->sigma12};
@@ -359,18 +373,27 @@ tlb_status tlb3_read_fields(tlb3_ctx* c, uint32_t mask, double* out) {
     if (mask == 0 || (mask & ~uint32_t(TLB3_F_ALL))) return fail(c, TLB_EINVAL, "bad field mask");
     if (!c->inited) return fail(c, TLB_ESTATE, "init_fields must precede read_fields");
     const size_t n = c->L.n;
+    const size_t plane = size_t(c->nx) * c->ny;
     double* stage = stage_ptr(c);
-    hipError_t e = launch3_readout(c->prec, c->grid, consts_ptr(c), bufs_ptr(c), c->cur, stage,
-                                   c->stream);
+    hipError_t e = launch3_c_mu(c->prec, c->grid, consts_ptr(c), bufs_ptr(c), c->cur, c->stream);
     if (e != hipSuccess) return dev_fail(c, e, "readout kernels");
-    int o = 0;
-    for (int f = 0; f < 11; ++f) {
-        if (!(mask & (1u << f))) continue;
-        e = hipMemcpyAsync(out + size_t(o) * n, stage + size_t(f) * n, n * sizeof(double),
-                           hipMemcpyDeviceToHost, c->stream);
-        if (e != hipSuccess) return dev_fail(c, e, "readout copy");
-        ++o;
+    // bands of z-planes whose 11 fields fit the staging area; stream order
+    // keeps each band's copies ahead of the next band's kernel
+    const int band = int(std::min<size_t>(size_t(c->nz), c->L.stage_doubles / (11 * plane)));
+    for (int za = 0; za < c->nz && e == hipSuccess; za += band) {
+        const int zb = std::min(c->nz, za + band);
+        const size_t nb = size_t(zb - za) * plane;
+        e = launch3_readout(c->prec, c->grid, consts_ptr(c), bufs_ptr(c), c->cur, za, zb, stage,
+                            c->stream);
+        int o = 0;
+        for (int f = 0; f < 11 && e == hipSuccess; ++f) {
+            if (!(mask & (1u << f))) continue;
+            e = hipMemcpyAsync(out + size_t(o) * n + size_t(za) * plane, stage + size_t(f) * nb,
+                               nb * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+            ++o;
+        }
     }
+    if (e != hipSuccess) return dev_fail(c, e, "readout");
     e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return dev_fail(c, e, "readout sync");
     return TLB_OK;
@@ -380,16 +403,23 @@ tlb_status tlb3_read_populations(tlb3_ctx* c, double* out) {
     if (!c || !out) return fail(c, TLB_EINVAL, "null pointer");
     if (!c->inited) return fail(c, TLB_ESTATE, "init_fields must precede read_populations");
     const size_t n = c->L.n;
+    const size_t plane = size_t(c->nx) * c->ny;
     double* stage = stage_ptr(c);
-    for (int fam = 0; fam < 3; ++fam) {
-        hipError_t e = launch3_populations(c->prec, c->grid, bufs_ptr(c), c->cur, fam, stage,
-                                           c->stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(out + size_t(fam) * kQ * n, stage, kQ * n * sizeof(double),
-                               hipMemcpyDeviceToHost, c->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-        if (e != hipSuccess) return dev_fail(c, e, "populations readout");
-    }
+    const int band = int(std::min<size_t>(size_t(c->nz), c->L.stage_doubles / (kQ * plane)));
+    hipError_t e = hipSuccess;
+    for (int fam = 0; fam < 3 && e == hipSuccess; ++fam)
+        for (int za = 0; za < c->nz && e == hipSuccess; za += band) {
+            const int zb = std::min(c->nz, za + band);
+            const size_t nb = size_t(zb - za) * plane;
+            e = launch3_populations(c->prec, c->grid, bufs_ptr(c), c->cur, fam, za, zb, stage,
+                                    c->stream);
+            for (int k = 0; k < kQ && e == hipSuccess; ++k)
+                e = hipMemcpyAsync(out + (size_t(fam) * kQ + k) * n + size_t(za) * plane,
+                                   stage + size_t(k) * nb, nb * sizeof(double),
+                                   hipMemcpyDeviceToHost, c->stream);
+        }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return dev_fail(c, e, "populations readout");
     return TLB_OK;
 }
 

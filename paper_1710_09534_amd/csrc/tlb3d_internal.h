@@ -60,12 +60,14 @@ hipError_t launch3_c_mu(int prec, const Grid3& g, const void* consts, const void
 // equilibrium populations into buffer 0 and history from in5 (ux, uy, uz)
 hipError_t launch3_init(int prec, const Grid3& g, const void* consts, const void* bufs,
                         const double* in5, hipStream_t s);
-// fields c1 c2 c3 rho ux uy uz p mu1 mu2 mu3 (11 x n doubles) of buffer cur
+// fields c1 c2 c3 rho ux uy uz p mu1 mu2 mu3 of buffer cur on the planes
+// [za, zb) (11 x nx*ny*(zb-za) doubles); launch3_c_mu must have run on cur
 hipError_t launch3_readout(int prec, const Grid3& g, const void* consts, const void* bufs,
-                           int cur, double* out11, hipStream_t s);
-// populations of family fam (f^1, f^2, g) of buffer cur: 19 x n doubles
+                           int cur, int za, int zb, double* out11, hipStream_t s);
+// populations of family fam (f^1, f^2, g) of buffer cur on the planes
+// [za, zb): 19 x nx*ny*(zb-za) doubles
 hipError_t launch3_populations(int prec, const Grid3& g, const void* bufs, int cur, int fam,
-                               double* out19, hipStream_t s);
+                               int za, int zb, double* out19, hipStream_t s);
 hipError_t launch3_mass(int prec, const Grid3& g, const void* bufs, int cur, double* partials,
                         double* result, hipStream_t s);
 

@@ -582,13 +582,14 @@ __global__ __launch_bounds__(256) void init3_kernel(Grid3 g, Consts3<R> c, Bufs3
 // ------------------------------------------------------------------ readout
 template <typename R>
 __global__ __launch_bounds__(256) void read3_kernel(Grid3 g, Consts3<R> c, Bufs3<R> b, int cur,
-                                                    double* out) {
-    const Node nd = node_of(g);
-    if (!nd.in) return;
+                                                    int za, int zb, double* out) {
+    Node nd = node_of(g);                      // blockIdx.z counts planes from za
+    nd.z += za;
+    if (!nd.in || nd.z >= zb) return;
     const Nb3 nb = make_nb3(g, nd.x, nd.y, nd.z);
     const long long i = nb.at(0, 0, 0);
-    const long long hi = ((long long)nd.z * g.ny + nd.y) * g.nx + nd.x;
-    const long long n = (long long)g.nx * g.ny * g.nz;
+    const long long hi = ((long long)(nd.z - za) * g.ny + nd.y) * g.nx + nd.x;
+    const long long n = (long long)g.nx * g.ny * (zb - za);
     if (b.mat[i]) {
         for (int f = 0; f < 11; ++f) out[f * n + hi] = 0.0;
         return;
@@ -606,16 +607,18 @@ __global__ __launch_bounds__(256) void read3_kernel(Grid3 g, Consts3<R> c, Bufs3
     for (int f = 0; f < 11; ++f) out[f * n + hi] = v[f];
 }
 
-// populations f(x) of family fam (19 planes), pulled; walls read 0
+// populations f(x) of family fam (19 planes) on the planes [za, zb), pulled;
+// walls read 0
 template <typename R>
 __global__ __launch_bounds__(256) void pops3_kernel(Grid3 g, Bufs3<R> b, int cur, int fam,
-                                                    double* out) {
-    const Node nd = node_of(g);
-    if (!nd.in) return;
+                                                    int za, int zb, double* out) {
+    Node nd = node_of(g);
+    nd.z += za;
+    if (!nd.in || nd.z >= zb) return;
     const Nb3 nb = make_nb3(g, nd.x, nd.y, nd.z);
     const long long i = nb.at(0, 0, 0);
-    const long long hi = ((long long)nd.z * g.ny + nd.y) * g.nx + nd.x;
-    const long long n = (long long)g.nx * g.ny * g.nz;
+    const long long hi = ((long long)(nd.z - za) * g.ny + nd.y) * g.nx + nd.x;
+    const long long n = (long long)g.nx * g.ny * (zb - za);
     const bool wall = b.mat[i] != 0;
     const R* __restrict__ P = b.pop[cur];
 #pragma unroll
@@ -719,13 +722,13 @@ hipError_t init_r(const Grid3& g, const void* consts, const void* bufs, const do
 }
 
 template <typename R>
-hipError_t read_r(const Grid3& g, const void* consts, const void* bufs, int cur, double* out,
-                  hipStream_t s) {
-    hipError_t e = c_mu_r<R>(g, consts, bufs, cur, s);
-    if (e != hipSuccess) return e;
+hipError_t read_r(const Grid3& g, const void* consts, const void* bufs, int cur, int za, int zb,
+                  double* out, hipStream_t s) {
     const Consts3<R>& c = *static_cast<const Consts3<R>*>(consts);
     const Bufs3<R>& b = *static_cast<const Bufs3<R>*>(bufs);
-    hipLaunchKernelGGL((read3_kernel<R>), grid_of(g), dim3(256), 0, s, g, c, b, cur, out);
+    dim3 gr = grid_of(g);
+    gr.z = unsigned(zb - za);
+    hipLaunchKernelGGL((read3_kernel<R>), gr, dim3(256), 0, s, g, c, b, cur, za, zb, out);
     return hipGetLastError();
 }
 
@@ -750,19 +753,23 @@ hipError_t launch3_init(int prec, const Grid3& g, const void* consts, const void
 }
 
 hipError_t launch3_readout(int prec, const Grid3& g, const void* consts, const void* bufs,
-                           int cur, double* out11, hipStream_t s) {
-    return prec == 0 ? read_r<double>(g, consts, bufs, cur, out11, s)
-                     : read_r<float>(g, consts, bufs, cur, out11, s);
+                           int cur, int za, int zb, double* out11, hipStream_t s) {
+    if (za < 0 || zb > g.nz || za >= zb) return hipErrorInvalidValue;
+    return prec == 0 ? read_r<double>(g, consts, bufs, cur, za, zb, out11, s)
+                     : read_r<float>(g, consts, bufs, cur, za, zb, out11, s);
 }
 
 hipError_t launch3_populations(int prec, const Grid3& g, const void* bufs, int cur, int fam,
-                               double* out19, hipStream_t s) {
+                               int za, int zb, double* out19, hipStream_t s) {
+    if (za < 0 || zb > g.nz || za >= zb) return hipErrorInvalidValue;
+    dim3 gr = grid_of(g);
+    gr.z = unsigned(zb - za);
     if (prec == 0)
-        hipLaunchKernelGGL((pops3_kernel<double>), grid_of(g), dim3(256), 0, s, g,
-                           *static_cast<const Bufs3<double>*>(bufs), cur, fam, out19);
+        hipLaunchKernelGGL((pops3_kernel<double>), gr, dim3(256), 0, s, g,
+                           *static_cast<const Bufs3<double>*>(bufs), cur, fam, za, zb, out19);
     else
-        hipLaunchKernelGGL((pops3_kernel<float>), grid_of(g), dim3(256), 0, s, g,
-                           *static_cast<const Bufs3<float>*>(bufs), cur, fam, out19);
+        hipLaunchKernelGGL((pops3_kernel<float>), gr, dim3(256), 0, s, g,
+                           *static_cast<const Bufs3<float>*>(bufs), cur, fam, za, zb, out19);
     return hipGetLastError();
 }
 

@@ -5,6 +5,7 @@
 // checkpoint calls.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -30,6 +31,7 @@ struct Layout {
     size_t rest_off;    // P16: offset of the two FP32 rest planes inside a lattice
     size_t hist_bytes;
     size_t off_pop[2], off_hist, off_mat, off_mtab, off_desc, off_stage, off_part, off_result;
+    size_t stage_doubles;
     size_t total;
 };
 
@@ -51,7 +53,10 @@ Layout make_layout(int nx, int ny, int prec) {
     L.off_mat = o; o += align_up(L.npad, kAlign);
     L.off_mtab = o; o += align_up(kMatStride * (kMaxMaterials + 1) * sizeof(double), kAlign);
     L.off_desc = o; o += kDescBytes;
-    L.off_stage = o; o += align_up(size_t(27) * nx * ny * sizeof(double), kAlign);
+    // staging: the 4 input fields of init; readout and population copies pass
+    // through it in bands of rows (at least one row of 27 planes)
+    L.stage_doubles = std::max(size_t(4) * nx * ny, size_t(27) * nx);
+    L.off_stage = o; o += align_up(L.stage_doubles * sizeof(double), kAlign);
     L.off_part = o; o += align_up(kReduceBlocks * 4 * sizeof(double), kAlign);
     L.off_result = o; o += kAlign;
     L.total = o;
@@ -227,9 +232,17 @@ void poll_health(tlb_ctx* c) {
 
 extern "C" {
 
+// the step kernel addresses each family of 9 planes (and the history) as one
+// buffer with 32-bit offsets and discards stores at offset 2^31
+static bool fits_offsets(const Layout& L, int p) {
+    return 9 * L.npad * elem_bytes(p) < (size_t(1) << 31) &&
+           4 * L.npad * (p == TLB_FP64 ? 8 : 4) < (size_t(1) << 31);
+}
+
 size_t tlb_workspace_bytes(int nx, int ny, tlb_precision p) {
     if (nx < 3 || ny < 3 || (p != TLB_FP64 && p != TLB_FP32 && p != TLB_FP16DEV)) return 0;
-    return make_layout(nx, ny, int(p)).total;
+    const Layout L = make_layout(nx, ny, int(p));
+    return fits_offsets(L, int(p)) ? L.total : 0;
 }
 
 tlb_status tlb_create(int nx, int ny, tlb_precision p, const tlb_fluid* fl, void* dev_workspace,
@@ -243,10 +256,7 @@ tlb_status tlb_create(int nx, int ny, tlb_precision p, const tlb_fluid* fl, void
     if (reinterpret_cast<uintptr_t>(dev_workspace) % kAlign)
         return fail(nullptr, TLB_EINVAL, "workspace not 256-byte aligned");
     Layout L = make_layout(nx, ny, int(p));
-    // the step kernel addresses each family of 9 planes (and the history) as
-    // one buffer with 32-bit offsets and discards stores at offset 2^31
-    if (9 * L.npad * elem_bytes(int(p)) >= (size_t(1) << 31) ||
-        4 * L.npad * (p == TLB_FP64 ? 8 : 4) >= (size_t(1) << 31))
+    if (!fits_offsets(L, int(p)))
         return fail(nullptr, TLB_EINVAL, "lattice too large: a family of 9 planes must stay below 2 GiB");
     if (ws_bytes < L.total) return fail(nullptr, TLB_ENOMEM, "workspace too small");
     // Eq. 7, Eq. 9
@@ -486,19 +496,27 @@ tlb_status tlb_read_fields(tlb_ctx* c, uint32_t mask, double* out) {
     if (!c->inited) return fail(c, TLB_ESTATE, "init_fields must precede read_fields");
     const size_t n = size_t(c->nx) * c->ny;
     double* stage = reinterpret_cast<double*>(c->ws + c->L.off_stage);
-    hipError_t e = launch_readout(c->prec, c->grid, consts_ptr(c),
-                                  reinterpret_cast<uint8_t*>(c->ws + c->L.off_mat),
-                                  reinterpret_cast<double*>(c->ws + c->L.off_mtab), popbuf(c, c->cur),
-                                  c->ws + c->L.off_hist, stage, c->stream);
-    if (e != hipSuccess) return dev_fail(c, e, "readout kernel");
-    int o = 0;
-    for (int f = 0; f < 10; ++f) {
-        if (!(mask & (1u << f))) continue;
-        e = hipMemcpyAsync(out + size_t(o) * n, stage + size_t(f) * n, n * sizeof(double),
-                           hipMemcpyDeviceToHost, c->stream);
-        if (e != hipSuccess) return dev_fail(c, e, "readout copy");
-        ++o;
+    // bands of rows whose 10 fields fit the staging area; stream order keeps
+    // each band's copies ahead of the next band's kernel
+    const int band = int(std::min<size_t>(size_t(c->ny), c->L.stage_doubles / (10 * size_t(c->nx))));
+    hipError_t e = hipSuccess;
+    for (int ya = 0; ya < c->ny && e == hipSuccess; ya += band) {
+        const int yb = std::min(c->ny, ya + band);
+        const size_t nb = size_t(yb - ya) * c->nx;
+        e = launch_readout(c->prec, c->grid, consts_ptr(c),
+                           reinterpret_cast<uint8_t*>(c->ws + c->L.off_mat),
+                           reinterpret_cast<double*>(c->ws + c->L.off_mtab), popbuf(c, c->cur), ya,
+                           yb, stage, c->stream);
+        if (e != hipSuccess) return dev_fail(c, e, "readout kernel");
+        int o = 0;
+        for (int f = 0; f < 10 && e == hipSuccess; ++f) {
+            if (!(mask & (1u << f))) continue;
+            e = hipMemcpyAsync(out + size_t(o) * n + size_t(ya) * c->nx, stage + size_t(f) * nb,
+                               nb * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+            ++o;
+        }
     }
+    if (e != hipSuccess) return dev_fail(c, e, "readout copy");
     e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return dev_fail(c, e, "readout sync");
     return TLB_OK;
@@ -509,11 +527,18 @@ tlb_status tlb_read_populations(tlb_ctx* c, double* out) {
     if (!c->inited) return fail(c, TLB_ESTATE, "init_fields must precede read_populations");
     const size_t n = size_t(c->nx) * c->ny;
     double* stage = reinterpret_cast<double*>(c->ws + c->L.off_stage);
-    hipError_t e = launch_populations(c->prec, c->grid, consts_ptr(c),
-                                      reinterpret_cast<uint8_t*>(c->ws + c->L.off_mat),
-                                      popbuf(c, c->cur), stage, c->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(out, stage, 27 * n * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    const int band = int(std::min<size_t>(size_t(c->ny), c->L.stage_doubles / (27 * size_t(c->nx))));
+    hipError_t e = hipSuccess;
+    for (int ya = 0; ya < c->ny && e == hipSuccess; ya += band) {
+        const int yb = std::min(c->ny, ya + band);
+        const size_t nb = size_t(yb - ya) * c->nx;
+        e = launch_populations(c->prec, c->grid, consts_ptr(c),
+                               reinterpret_cast<uint8_t*>(c->ws + c->L.off_mat), popbuf(c, c->cur),
+                               ya, yb, stage, c->stream);
+        for (int q = 0; q < 27 && e == hipSuccess; ++q)
+            e = hipMemcpyAsync(out + size_t(q) * n + size_t(ya) * c->nx, stage + size_t(q) * nb,
+                               nb * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return dev_fail(c, e, "read_populations");
     return TLB_OK;

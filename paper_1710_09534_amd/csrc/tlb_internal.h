@@ -88,11 +88,14 @@ hipError_t launch_step(int prec, unsigned features, const void* descs, int ndesc
 hipError_t launch_init(int prec, const Grid& g, const void* consts, const uint8_t* mat,
                        const double* mtab, const double* in4, PopBuf dst, void* hist,
                        hipStream_t s);
+// fields of the rows [ya, yb): out10[10][(yb - ya) * nx]
 hipError_t launch_readout(int prec, const Grid& g, const void* consts, const uint8_t* mat,
-                          const double* mtab, PopBuf src, void* hist, double* out10,
+                          const double* mtab, PopBuf src, int ya, int yb, double* out10,
                           hipStream_t s);
+// populations of the rows [ya, yb): out27[27][(yb - ya) * nx]
 hipError_t launch_populations(int prec, const Grid& g, const void* consts,
-                              const uint8_t* mat, PopBuf src, double* out27, hipStream_t s);
+                              const uint8_t* mat, PopBuf src, int ya, int yb, double* out27,
+                              hipStream_t s);
 hipError_t launch_mass(int prec, const Grid& g, const void* consts, const uint8_t* mat,
                        PopBuf src, double* partials, double* result, hipStream_t s);
 

@@ -1045,14 +1045,15 @@ template <int P, int TY>
 __global__ __launch_bounds__(kThreads) void readout_kernel(Grid g, Consts<typename Tr<P>::R> c,
                                                            const uint8_t* __restrict__ mat,
                                                            const double* __restrict__ mtab,
-                                                           PopBuf src, double* __restrict__ out) {
+                                                           PopBuf src, int ya, int yb,
+                                                           double* __restrict__ out) {
     using R = typename Tr<P>::R;
     using SM = Smem<P, TY>;
     __shared__ SM sm;
     const int t = blockIdx.x;
     const int ntx = (g.nx + kTileX - 1) / kTileX;
     const int x0 = (t % ntx) * kTileX;
-    const int y0 = (t / ntx) * TY;
+    const int y0 = ya + (t / ntx) * TY;
     load_mtab<P, TY>(sm, mtab);
     phase_a<P, TY, true>(sm, g, c, mat, src, nullptr, x0, y0);
     __syncthreads();
@@ -1061,13 +1062,13 @@ __global__ __launch_bounds__(kThreads) void readout_kernel(Grid g, Consts<typena
     const int tx = threadIdx.x & (kTileX - 1);
     const int gx = x0 + tx;
     if (gx >= g.nx) return;
-    const long n = long(g.nx) * g.ny;
+    const long n = long(g.nx) * (yb - ya);               // nodes of the band
     for (int ty = threadIdx.x / kTileX; ty < TY; ty += kThreads / kTileX) {
         const int gy = y0 + ty;
-        if (gy >= g.ny) break;
+        if (gy >= yb) break;
         const int ci = (ty + 2) * SM::CW + tx + 2;
         const int mi = (ty + 1) * SM::MW + tx + 1;
-        const long hi = long(gy) * g.nx + gx;
+        const long hi = long(gy - ya) * g.nx + gx;
         if (sm.m[ci]) {
             for (int f = 0; f < 10; ++f) out[f * n + hi] = 0.0;
             continue;
@@ -1091,14 +1092,17 @@ __global__ __launch_bounds__(kThreads) void readout_kernel(Grid g, Consts<typena
 }
 
 // ------------------------------------------------------------ populations
+// f(x) of the rows [ya, yb) as doubles, [27][(yb - ya) * nx]
 template <int P>
 __global__ __launch_bounds__(kThreads) void populations_kernel(Grid g, Consts<typename Tr<P>::R> c,
                                                                const uint8_t* __restrict__ mat,
-                                                               PopBuf src, double* __restrict__ out) {
-    const long n = long(g.nx) * g.ny;
+                                                               PopBuf src, int ya, int yb,
+                                                               double* __restrict__ out) {
+    const long n = long(g.nx) * (yb - ya);
     for (long hi = long(blockIdx.x) * kThreads + threadIdx.x; hi < n;
          hi += long(gridDim.x) * kThreads) {
-        const int gy = int(hi / g.nx), gx = int(hi - long(gy) * g.nx);
+        const int by = int(hi / g.nx), gx = int(hi - long(by) * g.nx);
+        const int gy = ya + by;
         const Nb nb = make_nb(g, gx, gy);
         const bool solid = mat[nb.r0 + gx] != 0;
 #pragma unroll
@@ -1225,41 +1229,44 @@ hipError_t launch_init(int prec, const Grid& g, const void* consts, const uint8_
 
 template <int P>
 static hipError_t readout_p(const Grid& g, const void* consts, const uint8_t* mat,
-                            const double* mtab, PopBuf src, double* out, hipStream_t s) {
-    int nt = ((g.nx + kTileX - 1) / kTileX) * ((g.ny + kAuxRows - 1) / kAuxRows);
+                            const double* mtab, PopBuf src, int ya, int yb, double* out,
+                            hipStream_t s) {
+    int nt = ((g.nx + kTileX - 1) / kTileX) * ((yb - ya + kAuxRows - 1) / kAuxRows);
     hipLaunchKernelGGL((readout_kernel<P, kAuxRows>), dim3(nt), dim3(kThreads), 0, s, g,
-                       *static_cast<const CT<P>*>(consts), mat, mtab, src, out);
+                       *static_cast<const CT<P>*>(consts), mat, mtab, src, ya, yb, out);
     return hipGetLastError();
 }
 
 hipError_t launch_readout(int prec, const Grid& g, const void* consts, const uint8_t* mat,
-                          const double* mtab, PopBuf src, void* /*hist*/, double* out10,
+                          const double* mtab, PopBuf src, int ya, int yb, double* out10,
                           hipStream_t s) {
+    if (ya < 0 || yb > g.ny || ya >= yb) return hipErrorInvalidValue;
     switch (prec) {
-        case P64: return readout_p<P64>(g, consts, mat, mtab, src, out10, s);
-        case P32: return readout_p<P32>(g, consts, mat, mtab, src, out10, s);
-        case P16: return readout_p<P16>(g, consts, mat, mtab, src, out10, s);
+        case P64: return readout_p<P64>(g, consts, mat, mtab, src, ya, yb, out10, s);
+        case P32: return readout_p<P32>(g, consts, mat, mtab, src, ya, yb, out10, s);
+        case P16: return readout_p<P16>(g, consts, mat, mtab, src, ya, yb, out10, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <int P>
 static hipError_t pops_p(const Grid& g, const void* consts, const uint8_t* mat, PopBuf src,
-                         double* out, hipStream_t s) {
-    long n = long(g.nx) * g.ny;
+                         int ya, int yb, double* out, hipStream_t s) {
+    long n = long(g.nx) * (yb - ya);
     int nb = int((n + kThreads - 1) / kThreads);
     if (nb > 4096) nb = 4096;
     hipLaunchKernelGGL((populations_kernel<P>), dim3(nb), dim3(kThreads), 0, s, g,
-                       *static_cast<const CT<P>*>(consts), mat, src, out);
+                       *static_cast<const CT<P>*>(consts), mat, src, ya, yb, out);
     return hipGetLastError();
 }
 
 hipError_t launch_populations(int prec, const Grid& g, const void* consts, const uint8_t* mat,
-                              PopBuf src, double* out27, hipStream_t s) {
+                              PopBuf src, int ya, int yb, double* out27, hipStream_t s) {
+    if (ya < 0 || yb > g.ny || ya >= yb) return hipErrorInvalidValue;
     switch (prec) {
-        case P64: return pops_p<P64>(g, consts, mat, src, out27, s);
-        case P32: return pops_p<P32>(g, consts, mat, src, out27, s);
-        case P16: return pops_p<P16>(g, consts, mat, src, out27, s);
+        case P64: return pops_p<P64>(g, consts, mat, src, ya, yb, out27, s);
+        case P32: return pops_p<P32>(g, consts, mat, src, ya, yb, out27, s);
+        case P16: return pops_p<P16>(g, consts, mat, src, ya, yb, out27, s);
         default: return hipErrorInvalidValue;
     }
 }

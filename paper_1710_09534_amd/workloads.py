@@ -361,6 +361,67 @@ def bandwidth_case(nx, ny):
                     z, z, steps=500)
 
 
+def large_lattice(nx, ny, seed=5):
+    """Fully periodic three-phase lattice for size-limit tests: a smooth
+    background mixture of all three phases (integer Fourier modes of about
+    100-node wavelength, so it is periodic), a slow shear-like velocity, and
+    five features, each a staircase cylinder of one of two wetting materials
+    with a phase-1 and a phase-2 drop resting on it and on each other.  The
+    features sit across the periodic corner, on the right edge (the ragged
+    last strip column when nx is not a multiple of 64), on the top edge, in
+    the centre, and near the bottom-right corner.  ``features`` lists their
+    bounding boxes (x0, y0, w, h) for sampling."""
+    rng = Rng(seed)
+    x = np.arange(nx, dtype=np.float64)
+    y = np.arange(ny, dtype=np.float64)
+
+    def mode(n, coord):
+        k = max(1, n // 100) + rng.choice(3)
+        return np.sin(2.0 * math.pi * k * coord / n + rng.uniform(0.0, 2.0 * math.pi))
+
+    c1 = np.multiply.outer(mode(ny, y), mode(nx, x))
+    c1 *= 0.15
+    c1 += 1.0 / 3.0
+    c2 = np.multiply.outer(mode(ny, y), mode(nx, x))
+    c2 *= 0.15
+    c2 += 1.0 / 3.0
+    ux = np.multiply.outer(mode(ny, y), np.full(nx, 0.004))
+    uy = np.multiply.outer(np.full(ny, 0.003), mode(nx, x))
+    mask = np.zeros((ny, nx), dtype=np.uint8)
+    centres = [(0, 0), (nx - 1, ny // 2), (nx // 2, ny - 1), (nx // 2, ny // 2),
+               (nx - 40, 40)]
+    D = 4.0
+    features = []
+    for i, (xc, yc) in enumerate(centres):
+        Rc, Rd = 10.0 + 2 * i, 14.0
+        phase = 1 + (i % 2)
+        drops = [(xc + Rc + Rd - 3.0, yc + 4.0, phase),
+                 (xc + Rc + Rd - 3.0, yc + 4.0 + 2 * Rd - 4.0, 3 - phase)]
+        bx0, by0 = int(xc - Rc - 8), int(yc - Rc - 8)
+        w = int(Rc + 2 * Rd + Rc + 24)
+        h = int(Rc + 4 * Rd + 24)
+        features.append((bx0 % nx, by0 % ny, w, h))
+        xs = np.arange(bx0, bx0 + w)
+        ys = np.arange(by0, by0 + h)
+        box = np.ix_(ys % ny, xs % nx)
+        X, Y = np.meshgrid(xs.astype(np.float64), ys.astype(np.float64))
+        b1, b2 = c1[box], c2[box]
+        for (dx, dy, ph) in drops:
+            d = 0.5 + 0.5 * np.tanh(2.0 * (Rd - np.hypot(X - dx, Y - dy)) / D)
+            b1 = (1.0 - d) * b1 + (d if ph == 1 else 0.0)
+            b2 = (1.0 - d) * b2 + (d if ph == 2 else 0.0)
+        c1[box], c2[box] = b1, b2
+        cyl = np.hypot(X - xc, Y - yc) <= Rc
+        mb = mask[box]
+        mb[cyl] = 1 + (i % 2)
+        mask[box] = mb
+    fl = fluid(sigma=(1e-3, 1.3e-3, 1.1e-3), D=D, M0=1e-4, tau=(0.8, 0.9), rho=(3.0, 2.0, 1.0),
+               nu=(0.1, 0.05, 0.15))
+    mats = [material(60.0, 100.0), material(120.0, 75.0)]
+    return _problem("large_%dx%d_s%d" % (nx, ny, seed), nx, ny, fl, (1, 1), mask, mats, c1, c2,
+                    ux, uy, steps=0, features=features)
+
+
 def serving_request(rng: Rng, n: int, kind: int, precision_steps=(1000, 20000)):
     """One serving request: a single (kind 0), binary (1) or compound (2)
     drop on the bottom wall of an n x n channel; contact angles ~ U[30, 150]

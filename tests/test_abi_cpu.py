@@ -133,3 +133,48 @@ def test_create3_rejections():
                              512, None, C.byref(h))
     assert st in (tlb.TLB_EINVAL, tlb.TLB_ENOMEM)
     assert not h.value
+
+
+def _max_rows(nx, elem, hist_elem, planes=9):
+    """Largest ny whose padded family of `planes` planes and 4-plane history
+    stay below 2 GiB (rows padded to a multiple of 64 nodes)."""
+    pitch = -(-nx // 64) * 64
+    lim = (1 << 31) - 1
+    return min(lim // (planes * pitch * elem), lim // (4 * pitch * hist_elem))
+
+
+@pytest.mark.parametrize("prec,nx,elem,hist", [(0, 5430, 8, 8), (1, 7710, 4, 4), (2, 10900, 2, 4)])
+def test_size_limit_boundary(prec, nx, elem, hist):
+    """tlb_workspace_bytes is non-zero up to the largest lattice tlb_create
+    accepts and 0 one row beyond it; tlb_create agrees."""
+    from paper_1710_09534_amd import tlb
+    ny = _max_rows(nx, elem, hist)
+    assert tlb.tlb_workspace_bytes(nx, ny, prec) > 0
+    assert tlb.tlb_workspace_bytes(nx, ny + 1, prec) == 0
+    f = tlb.make_fluid(_fl())
+    h = C.c_void_p()
+    assert tlb.lib.tlb_create(nx, ny + 1, prec, C.byref(f), C.c_void_p(256), 1 << 40, None,
+                              C.byref(h)) == tlb.TLB_EINVAL
+
+
+def test_workspace_is_lattice_plus_modest_staging():
+    """The staging area holds the 4 init fields, not a full copy of the
+    populations: workspace bytes per node stay close to the lattice's own
+    (FP16-dev also keeps the unused FP16 slots of the two rest planes, whose
+    values live in FP32 planes: 8 bytes per node)."""
+    from paper_1710_09534_amd import tlb
+    n = 1024 * 2048
+    for prec, lattice in ((0, 2 * 27 * 8 + 4 * 8 + 1), (1, 2 * 27 * 4 + 4 * 4 + 1),
+                          (2, 2 * (25 * 2 + 2 * 4) + 4 * 4 + 1)):
+        per_node = tlb.tlb_workspace_bytes(1024, 2048, prec) / n
+        assert lattice <= per_node <= lattice + 4 * 8 + 8 + 1, (prec, per_node)
+
+
+def test_size_limit_boundary_3d():
+    from paper_1710_09534_amd import tlb
+    for prec, elem in ((0, 8), (1, 4)):
+        nx, ny = 200, 150                      # pitch 256
+        nz = ((1 << 31) - 1) // (19 * 256 * ny * elem)
+        assert tlb.lib.tlb3_workspace_bytes(nx, ny, nz, prec) > 0
+        assert tlb.lib.tlb3_workspace_bytes(nx, ny, nz + 1, prec) == 0
+    assert tlb.lib.tlb3_workspace_bytes(64, 64, 65536, 1) == 0

@@ -193,3 +193,26 @@ def test_hydrostatic_pressure_in_stratified_layers():
         slope = np.polyfit(np.arange(a, b), pc[a:b], 1)[0]
         assert abs(slope + rho * g) <= 0.01 * rho * g, (rho, slope)
     assert np.abs(f["ux"]).max() < 1e-12 and np.abs(f["uy"]).max() < 1e-6
+
+
+@pytest.mark.parametrize("phase", [1, 2, 3])
+def test_single_phase_at_rest_is_a_fixed_point(phase):
+    """One phase filling the domain at rest: the bulk free energy and its
+    gradient terms vanish (Eq. 8 with c_phase = 1, the others 0), the
+    wetting ghosts (Eq. 42) of a pure phase equal the fluid value, so the
+    chemical potentials, forces, velocity and pressure stay exactly zero and
+    the order parameters exactly 0 / 1, next to walls of any wettability."""
+    p = W.random_fields(70, 40, geometry="cylinder")
+    fl = p["material"] == 0
+    one = np.where(fl, 1.0, 0.0)
+    zero = np.zeros_like(one)
+    c1 = one if phase == 1 else zero
+    c2 = one if phase == 2 else zero
+    o = oracle.Oracle(p)
+    o.init(c1, c2, zero, zero)
+    o.step(200)
+    f = o.fields()
+    assert np.array_equal(f["c1"], c1) and np.array_equal(f["c2"], c2)
+    assert np.array_equal(f["c3"], one if phase == 3 else zero)
+    for k in ("ux", "uy", "p", "mu1", "mu2", "mu3"):
+        assert not f[k].any(), k
