@@ -278,6 +278,10 @@ __device__ __forceinline__ R bload(rsrc_t r, unsigned vo, unsigned so) {
         return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, int(vo), int(so), 0));
 }
 
+// FP32 population stores are non-temporal (cache-policy operand bit 1):
+// written once per step and read once in the next, they then no longer evict
+// the halo lines that neighbouring tiles re-read from L2 (measured: 7 % less
+// step time in FP32; FP64 is 4 % slower with it and keeps the default).
 template <typename R>
 __device__ __forceinline__ void bstore(rsrc_t r, unsigned vo, unsigned so, R v) {
     if constexpr (sizeof(R) == 8)
@@ -285,7 +289,7 @@ __device__ __forceinline__ void bstore(rsrc_t r, unsigned vo, unsigned so, R v) 
             __builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)), v), r,
             int(vo), int(so), 0);
     else
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, int(vo), int(so), 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, int(vo), int(so), 2);
 }
 
 // neighbour values from the LDS rings: pointers of the node's position in
