@@ -361,6 +361,23 @@ def bandwidth_case(nx, ny):
                     z, z, steps=500)
 
 
+def floating_lens(nx=128, ny=128, R=20.0, sigma=(1e-2, 1e-2, 1e-2), D=4.0, M0=None, tau=0.8):
+    """Liquid lens (Sec. III.B, Eq. 49): a disc of phase 2 of radius R centred
+    on the flat interface y = ny/2 between a band of phase 1 (ny/8 <= y <
+    ny/2) and phase 3, in a fully periodic box.  Unit densities; sigma =
+    (sigma12, sigma13, sigma23)."""
+    x, y = coords(nx, ny)
+    yc = ny / 2.0
+    c2 = tanh_drop(nx, ny, nx / 2.0, yc, R, D)
+    band = (0.5 + 0.5 * np.tanh(2.0 * (yc - y) / D)) * (0.5 + 0.5 * np.tanh(2.0 * (y - ny / 8.0) / D))
+    c1 = (1.0 - c2) * band
+    mean_sigma = sum(sigma) / 3.0
+    fl = fluid(sigma=sigma, D=D, M0=(0.1 * mean_sigma if M0 is None else M0), tau=(tau, tau))
+    mask = np.zeros((ny, nx), dtype=np.uint8)
+    return _problem("lens_%dx%d_R%g" % (nx, ny, R), nx, ny, fl, (1, 1), mask, [], c1, c2,
+                    steps=0)
+
+
 def large_lattice(nx, ny, seed=5):
     """Fully periodic three-phase lattice for size-limit tests: a smooth
     background mixture of all three phases (integer Fourier modes of about

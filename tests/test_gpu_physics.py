@@ -77,3 +77,67 @@ def test_puddle_workload_parity(tlb):
     fg, fo = g.read_fields(), o.fields()
     d = {k: float(np.abs(fg[k] - fo[k]).max()) for k in fo}
     assert all(v <= 1e-12 for v in d.values()), d
+
+
+@pytest.fixture(scope="module")
+def lens_runs(tlb):
+    """The floating lens at 256 x 256 (R = 40) after 40000 steps in every
+    storage precision, equal and unequal tensions."""
+    out = {}
+    for name, sigma in (("equal", (1e-2, 1e-2, 1e-2)), ("unequal", (0.8e-2, 1e-2, 1.2e-2))):
+        p = W.floating_lens(256, 256, R=40.0, sigma=sigma)
+        for prec in ("fp64", "fp32", "fp16dev"):
+            print("case lens %s 256x256 steps=40000 %s" % (name, prec), flush=True)
+            g = tlb.from_problem(p, prec)
+            g.step(40000)
+            f = g.read_fields(tlb.F_ALL)
+            out[name, prec] = (sigma, f)
+    return out
+
+
+@pytest.mark.parametrize("name", ["equal", "unequal"])
+def test_lens_neumann_angles_gpu(lens_runs, name):
+    """Neumann's triangle (Eq. 49) and the two-arc lens shape on the GPU in
+    FP64: angles within 2 deg, Laplace ratio of the arcs' radii within 3 %,
+    thickness within 2 %, length within 4 % (a lens twice the oracle pin's
+    size, so the diffuse triple point weighs less)."""
+    from lens_geometry import analytic, measure
+    sigma, f = lens_runs[name, "fp64"]
+    m = measure(f["c1"], f["c2"])
+    a = analytic(*sigma, area=float(f["c2"].sum()))
+    print("lens %s fp64: measured %s analytic %s" % (name, {k: round(v, 2) for k, v in m.items()},
+                                                     {k: round(v, 2) for k, v in a.items()}),
+          flush=True)
+    for k in ("phi1", "phi2", "phi3"):
+        assert abs(m[k] - a[k]) <= 2.0, (k, m, a)
+    assert abs(m["R23"] / m["R12"] / (sigma[2] / sigma[0]) - 1) <= 0.03, (m, a)
+    assert abs(m["H"] / a["H"] - 1) <= 0.02, (m, a)
+    assert abs(m["L"] / a["L"] - 1) <= 0.04, (m, a)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16dev"])
+@pytest.mark.parametrize("name", ["equal", "unequal"])
+def test_lens_angles_reduced_precision(lens_runs, name, prec):
+    """The mixed-precision bar on angles (0.5 deg): after 40000 steps the
+    triple-point angles of the FP32 and FP16-dev runs agree with those of
+    the FP64 run within 0.5 deg."""
+    from lens_geometry import measure
+    _, f64 = lens_runs[name, "fp64"]
+    _, f = lens_runs[name, prec]
+    m64, m = measure(f64["c1"], f64["c2"]), measure(f["c1"], f["c2"])
+    d = {k: abs(m[k] - m64[k]) for k in ("phi1", "phi2", "phi3")}
+    print("lens %s %s: angle differences to fp64 %s" % (name, prec, d), flush=True)
+    assert all(v <= 0.5 for v in d.values()), (d, m, m64)
+
+
+def test_lens_parity(tlb):
+    """The lens setup itself, GPU FP64 against the oracle for 1000 steps."""
+    p = W.floating_lens(128, 128, R=20.0, sigma=(0.8e-2, 1e-2, 1.2e-2))
+    g = tlb.from_problem(p)
+    o = oracle.Oracle(p)
+    o.init(p["c1"], p["c2"], None, None)
+    g.step(1000)
+    o.step(1000)
+    fg, fo = g.read_fields(), o.fields()
+    d = {k: float(np.abs(fg[k] - fo[k]).max()) for k in fo}
+    assert all(v <= 1e-12 for v in d.values()), d

@@ -216,3 +216,28 @@ def test_single_phase_at_rest_is_a_fixed_point(phase):
     assert np.array_equal(f["c3"], one if phase == 3 else zero)
     for k in ("ux", "uy", "p", "mu1", "mu2", "mu3"):
         assert not f[k].any(), k
+
+
+@pytest.mark.parametrize("sigma", [(1e-2, 1e-2, 1e-2), (0.8e-2, 1e-2, 1.2e-2)],
+                         ids=["equal", "unequal"])
+def test_floating_lens_neumann_angles(sigma):
+    """A phase-2 lens on the flat 1|3 interface (Sec. III.B): after 10000
+    steps on 128 x 128 the angles at the triple points follow Neumann's
+    triangle (Eq. 49; 120 deg each for equal tensions, as the paper states)
+    within 3 deg, the arcs' radii have the Laplace ratio sigma23/sigma12
+    within 4 %, and the lens thickness and length match the two-arc shape of
+    the same area within 3 % and 6 % (the diffuse triple point shortens the
+    length)."""
+    from lens_geometry import analytic, measure
+    p = W.floating_lens(128, 128, R=20.0, sigma=sigma)
+    o = oracle.Oracle(p)
+    o.init(p["c1"], p["c2"], None, None)
+    o.step(10000)
+    f = o.fields()
+    m = measure(f["c1"], f["c2"])
+    a = analytic(*sigma, area=float(f["c2"].sum()))
+    for k in ("phi1", "phi2", "phi3"):
+        assert abs(m[k] - a[k]) <= 3.0, (k, m, a)
+    assert abs(m["R23"] / m["R12"] / (sigma[2] / sigma[0]) - 1) <= 0.04, (m, a)
+    assert abs(m["H"] / a["H"] - 1) <= 0.03, (m, a)
+    assert abs(m["L"] / a["L"] - 1) <= 0.06, (m, a)
