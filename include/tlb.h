@@ -188,9 +188,11 @@ tlb_status tlb_time_steps(tlb_ctx* ctx, int64_t nsteps, double* ms_per_step);
 
 /* Rows of the strip one workgroup of the step kernel marches through
  * (tuning knob; results are bitwise identical for every legal value).
- * rows: a multiple of 4 in [8, 4096].  Default: 64, or for a lattice too small
- * to give 256 strips of 64 rows, the tallest of 48, 32, 24, 16 that does (16
- * if none does). */
+ * rows: a multiple of 4 in [8, 4096].  Default, with C the device's compute
+ * units and W = 2 resident step workgroups per CU (1 in FP64): 128 when
+ * strips of 64 rows would outnumber C * W but strips of 128 rows would not;
+ * else 64 when that gives at least C strips; else the tallest of 48, 32, 24
+ * that does, or 16. */
 tlb_status tlb_set_tile_rows(tlb_ctx* ctx, int rows);
 
 /* Picks the strip height with the shortest step among candidate values

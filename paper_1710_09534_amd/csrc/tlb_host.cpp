@@ -153,12 +153,32 @@ void fill_consts(Consts<R>& k, const tlb_ctx* c) {
 // Default strip height: 64 rows, or the tallest of 48, 32, 24, 16 that still
 // gives the lattice one strip per compute unit (a lone small lattice
 // otherwise runs as a few workgroups each marching 64 rows in sequence).
-int default_rows(int nx, int ny) {
+// Default strip height.  A lattice that gives every workgroup slot of the
+// device a strip of 64 rows uses 64, or 128 when 128 fits all strips into
+// one round of resident workgroups and 64 does not (measured: FP64 at
+// 1024 x 2048 and FP32 at 2048 x 2048 run faster with one round of taller
+// strips than two rounds of 64-row ones).  Resident step workgroups per CU:
+// two in FP32 and FP16-dev (5 waves of 128 VGPRs), one in FP64 (224 VGPRs).
+// Smaller lattices take the tallest of 48, 32, 24, 16 rows that still gives
+// one strip per CU, so that a lone small lattice is not marched by a few
+// workgroups.
+int default_rows(int nx, int ny, int prec, int cus) {
     const int tx = (nx + kTileX - 1) / kTileX;
+    auto strips = [&](int rows) { return tx * ((ny + rows - 1) / rows); };
+    const int slots = cus * (prec == P64 ? 1 : 2);
+    if (strips(64) > slots && strips(128) <= slots) return 128;
     static const int cand[] = {64, 48, 32, 24};
     for (int rows : cand)
-        if (tx * ((ny + rows - 1) / rows) >= 256) return rows;
+        if (strips(rows) >= cus) return rows;
     return 16;
+}
+
+int device_cus() {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+        return 256;
+    return n;
 }
 
 void set_grid(tlb_ctx* c, int rows) {
@@ -297,7 +317,7 @@ tlb_status tlb_create(int nx, int ny, tlb_precision p, const tlb_fluid* fl, void
     c->eta[1] = c->M[1] / (cs2 * (fl->tau2 - 0.5));
     fill_consts(c->c64, c);
     fill_consts(c->c32, c);
-    set_grid(c, default_rows(nx, ny));
+    set_grid(c, default_rows(nx, ny, int(p), device_cus()));
     if (hipHostMalloc(reinterpret_cast<void**>(&c->health), 4 * sizeof(double)) != hipSuccess) {
         delete c;
         return fail(nullptr, TLB_ENOMEM, "pinned health word");
