@@ -77,8 +77,16 @@ def test_sessile_compound_drop_3d(tlb):
 
 
 def test_sphere_impact_medium_size(tlb):
-    """The sphere-impact setup at 96 x 96 x 128 (1.2 M nodes), few steps."""
+    """The sphere-impact setup at 96 x 96 x 128 (1.2 M nodes), 20 steps."""
     p = W.sphere_impact3d(nx=96, ny=96, nz=128, R_sphere=20.0, R_shell=16.0, R_core=8.0, We=50.0)
+    g, o = _pair(tlb, p, 20)
+    _check(g, o, pops=False)
+
+
+def test_sphere_impact_full_size(tlb):
+    """The benchmark's 192 x 192 x 256 sphere-impact lattice (9.4 M nodes),
+    3 steps in the launch configuration the benchmark times, every field."""
+    p = W.sphere_impact3d()
     g, o = _pair(tlb, p, 3)
     _check(g, o, pops=False)
 

@@ -78,10 +78,11 @@ def test_shear_small_fp64(tlb):
 
 
 def test_shear_full_size_fp64(tlb):
-    """The 400 x 150 shear setup of Sec. III.D (U0 = 0.1), few steps."""
+    """The 400 x 150 shear setup of Sec. III.D (U0 = 0.1), 1000 steps, every
+    field and population."""
     p = W.nee_shear()
-    g, o = _pair(tlb, p, 40)
-    _check(g, o, pops=False)
+    g, o = _pair(tlb, p, 1000)
+    _check(g, o)
 
 
 @pytest.mark.parametrize("nx,ny,top,bottom,u_top", [

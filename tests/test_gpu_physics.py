@@ -66,14 +66,14 @@ def test_puddle_thickness(tlb, g, tol1, tol2):
 
 def test_puddle_workload_parity(tlb):
     """The same 600 x 150 setup (density contrast 10/5/1, gravity) against
-    the oracle for 200 steps: every field within 1e-12."""
+    the oracle for 1000 steps: every field within 1e-12."""
     p = W.gravity_puddles(g=4e-5)
-    print("case %s parity 200 steps fp64" % p["name"], flush=True)
+    print("case %s parity 1000 steps fp64" % p["name"], flush=True)
     g = tlb.from_problem(p, "fp64")
     o = oracle.Oracle(p)
     o.init(p["c1"], p["c2"], p["ux"], p["uy"])
-    g.step(200)
-    o.step(200)
+    g.step(1000)
+    o.step(1000)
     fg, fo = g.read_fields(), o.fields()
     d = {k: float(np.abs(fg[k] - fo[k]).max()) for k in fo}
     assert all(v <= 1e-12 for v in d.values()), d
