@@ -577,6 +577,63 @@ def random_fields3(nx, ny, nz, seed=11, amp=0.2, geometry="channel", U=0.0,
                      periodic, mask, mats, c1, c2, u=(ux, uy, uz), gravity_z=gravity[2])
 
 
+def large_lattice3(nx, ny, nz, seed=5):
+    """Fully periodic three-phase D3Q19 lattice for size-limit tests: a
+    smooth background mixture of all three phases (products of integer
+    Fourier modes of about 60-node wavelength), a slow velocity field, and
+    four features, each a staircase ball of one of two wetting materials with
+    a phase-1 and a phase-2 drop resting on it and on each other, placed
+    across the periodic corner, on the ragged x edge, on the top edges and in
+    the centre.  ``features`` lists their boxes (x0, y0, z0, w, h, d)."""
+    rng = Rng(seed)
+
+    def mode(n):
+        k = max(1, n // 60) + rng.choice(2)
+        return np.sin(2.0 * math.pi * k * np.arange(n) / n + rng.uniform(0.0, 2.0 * math.pi))
+
+    def background(amp, off):
+        a = np.multiply.outer(np.multiply.outer(mode(nz), mode(ny)), mode(nx))
+        a *= amp
+        a += off
+        return a
+
+    c1 = background(0.15, 1.0 / 3.0)
+    c2 = background(0.15, 1.0 / 3.0)
+    ux = background(0.004, 0.0)
+    uy = background(0.003, 0.0)
+    uz = background(0.003, 0.0)
+    mask = np.zeros((nz, ny, nx), dtype=np.uint8)
+    centres = [(0, 0, 0), (nx - 1, ny // 2, nz // 2), (nx // 2, ny - 1, nz - 1),
+               (nx // 2, ny // 2, nz // 2)]
+    D = 4.0
+    features = []
+    for i, (xc, yc, zc) in enumerate(centres):
+        Rb, Rd = 7.0 + i, 9.0
+        phase = 1 + (i % 2)
+        drops = [(xc + Rb + Rd - 2.0, yc, zc + 2.0, phase),
+                 (xc + Rb + Rd - 2.0, yc, zc + 2.0 + 2 * Rd - 3.0, 3 - phase)]
+        x0, y0, z0 = int(xc - Rb - 6), int(yc - Rb - 6), int(zc - Rb - 6)
+        w, h, d = int(2 * Rb + 2 * Rd + 12), int(2 * Rb + 12), int(Rb + 4 * Rd + 12)
+        features.append((x0 % nx, y0 % ny, z0 % nz, w, h, d))
+        xs, ys, zs = np.arange(x0, x0 + w), np.arange(y0, y0 + h), np.arange(z0, z0 + d)
+        box = np.ix_(zs % nz, ys % ny, xs % nx)
+        Z, Y, X = np.meshgrid(zs.astype(float), ys.astype(float), xs.astype(float), indexing="ij")
+        b1, b2 = c1[box], c2[box]
+        for (dx, dy, dz, ph) in drops:
+            dd = 0.5 + 0.5 * np.tanh(2.0 * (Rd - np.sqrt((X - dx) ** 2 + (Y - dy) ** 2 + (Z - dz) ** 2)) / D)
+            b1 = (1.0 - dd) * b1 + (dd if ph == 1 else 0.0)
+            b2 = (1.0 - dd) * b2 + (dd if ph == 2 else 0.0)
+        c1[box], c2[box] = b1, b2
+        mb = mask[box]
+        mb[np.sqrt((X - xc) ** 2 + (Y - yc) ** 2 + (Z - zc) ** 2) <= Rb] = 1 + (i % 2)
+        mask[box] = mb
+    fl = fluid(sigma=(1e-3, 1.3e-3, 1.1e-3), D=D, M0=1e-4, tau=(0.8, 0.9), rho=(3.0, 2.0, 1.0),
+               nu=(0.1, 0.05, 0.15))
+    mats = [material(60.0, 100.0), material(120.0, 75.0)]
+    return _problem3("large3_%dx%dx%d_s%d" % (nx, ny, nz, seed), nx, ny, nz, fl, (1, 1, 1), mask,
+                     mats, c1, c2, u=(ux, uy, uz), features=features)
+
+
 def sessile3d(nx=128, ny=128, nz=64, R_core=16.0, R_shell=32.0, theta13=60.0, theta23=90.0,
               sigma=1e-3, steps=2000):
     """Compound drop (phase-1 core, phase-2 shell) resting on a wetting wall

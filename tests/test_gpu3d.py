@@ -127,3 +127,40 @@ def test_rejections_3d(tlb):
     with pytest.raises(tlb.TlbError) as e:
         s.step(1)
     assert e.value.status == tlb.TLB_ESTATE
+
+
+@pytest.mark.parametrize("precision,nx,elem", [("fp64", 200, 8), ("fp32", 300, 4)])
+def test_largest_lattice_sampled_3d(tlb, precision, nx, elem):
+    """The largest D3Q19 lattice each precision accepts (each 19-plane family
+    below 2 GiB; ragged width), 3 steps, compared on four feature boxes
+    (staircase balls of two wetting materials with drops of both phases,
+    across the periodic corner, on the ragged x edge, on the top edges and in
+    the centre) with cut-out oracle runs (tests/sampling.py, checked on the
+    oracle in tests/test_oracle_window.py).  FP64 within 1e-12 on every
+    field; FP32 within 1e-4 on the order parameters."""
+    from sampling import window_fields3
+    ny = nx
+    pitch = -(-nx // 64) * 64
+    nz = ((1 << 31) - 1) // (19 * elem * pitch * ny)
+    prec = tlb.PRECISIONS[precision]
+    assert tlb.lib.tlb3_workspace_bytes(nx, ny, nz, prec) > 0
+    assert tlb.lib.tlb3_workspace_bytes(nx, ny, nz + 1, prec) == 0
+    steps = 3
+    print("case largest 3-D %s %dx%dx%d (%.1f M nodes) steps=%d" % (precision, nx, ny, nz,
+                                                                  nx * ny * nz / 1e6, steps),
+          flush=True)
+    p = W.large_lattice3(nx, ny, nz)
+    g = tlb.from_problem3(p, precision)
+    g.step(steps)
+    names = tlb.FIELDS3 if precision == "fp64" else ("c1", "c2", "c3")
+    f = g.read_fields(names)
+    g.destroy()
+    worst = {}
+    for b in p["features"]:
+        b = b[:3] + tuple(min(v, 32) for v in b[3:])
+        wf, zs, ys, xs = window_fields3(oracle, p, b, 4 * steps + 8, steps)
+        for k in names:
+            worst[k] = max(worst.get(k, 0.0), float(np.abs(f[k][np.ix_(zs, ys, xs)] - wf[k]).max()))
+    print("max-abs over the windows:", worst, flush=True)
+    tol = TOL64 if precision == "fp64" else 1e-4
+    assert all(v <= tol for v in worst.values()), worst

@@ -55,3 +55,22 @@ def test_features_cover_walls_and_both_drops(case):
         m = p["material"][np.ix_(ys, xs)]
         assert (m != 0).any() and (m == 0).any()
         assert p["c1"][np.ix_(ys, xs)].max() > 0.9 and p["c2"][np.ix_(ys, xs)].max() > 0.9
+
+
+def test_cutout_reproduces_whole_lattice_3d():
+    """The same technique on the D3Q19 oracle: after 2 steps, cut-outs with
+    margin 4 s + 8 match the whole lattice bitwise on every field; a 1-node
+    margin does not."""
+    from sampling import window_fields3
+    p = W.large_lattice3(70, 60, 64, seed=2)
+    o = oracle.Oracle3D(p)
+    o.init(p["c1"], p["c2"], p["ux"], p["uy"], p["uz"])
+    o.step(2)
+    full = o.fields()
+    for b in p["features"]:
+        b = b[:3] + tuple(min(v, 24) for v in b[3:])
+        wf, zs, ys, xs = window_fields3(oracle, p, b, margin_for(2), 2)
+        for k in full:
+            assert np.array_equal(wf[k], full[k][np.ix_(zs, ys, xs)]), (k, b)
+    wf, zs, ys, xs = window_fields3(oracle, p, b, 1, 2)
+    assert max(float(np.abs(wf[k] - full[k][np.ix_(zs, ys, xs)]).max()) for k in wf) > 1e-9
