@@ -181,7 +181,8 @@ def batching_leg(tlb, torch, precision="fp32", n_lattices=256, size=64, steps=20
 
 
 def serving_leg(tlb, torch, precision="fp32", n_requests=120, steps=(1000, 4000),
-                arena_gb=40.0, slots=64, quantum=250, calibrate_sequential=False):
+                arena_gb=40.0, slots=64, quantum=250, calibrate_sequential=False,
+                loads=(0.7, 1.2), sequential=True):
     """A seeded stream of independent drop solves (sizes 64^2..1024^2
     weighted 0.40/0.30/0.15/0.10/0.05, single/binary/compound drops, random
     angles and surface tensions) served with continuous batching under an
@@ -190,7 +191,8 @@ def serving_leg(tlb, torch, precision="fp32", n_requests=120, steps=(1000, 4000)
     (FIFO, one request on the GPU at a time).  With calibrate_sequential the
     FP64 service time of each request is its size class's measured set-up
     time plus its steps times the class's measured time per step, instead
-    of running every request."""
+    of running every request.  loads: the Poisson loads to replay;
+    sequential=False skips the one-at-a-time FP64 comparison."""
     from paper_1710_09534_amd import workloads as W
     stream = W.serving_stream(n_requests, seed=2026, steps=steps)
     probs = [f() for (_, _, f) in stream]
@@ -227,13 +229,17 @@ def serving_leg(tlb, torch, precision="fp32", n_requests=120, steps=(1000, 4000)
            "arena_gb": arena_gb, "slots": slots, "quantum": quantum,
            "capacity_req_per_s": round(cap, 2),
            "closed_batch_mlups": round(work / makespan / 1e6, 1)}
-    for tag, load in (("load_0.7", 0.7), ("load_1.2", 1.2)):
+    for load in loads:
+        tag = "load_%g" % load
         arr = W.poisson_arrivals(len(probs), load * cap, seed=7)
         makespan, lat, st = run(arr, tag)
         out[tag] = {"p50_s": round(float(np.percentile(lat, 50)), 4),
                     "p99_s": round(float(np.percentile(lat, 99)), 4),
                     "aggregate_mlups": round(work / makespan / 1e6, 1),
                     "failed": int(st["failed"])}
+
+    if not sequential:
+        return out
 
     def solo(p, nsteps):
         torch.cuda.synchronize()
@@ -264,7 +270,8 @@ def serving_leg(tlb, torch, precision="fp32", n_requests=120, steps=(1000, 4000)
                                         for k, v in sorted(cal.items())}
     else:
         service = [solo(p, p["steps"]) for p in probs]
-    for tag, load in (("load_0.7", 0.7), ("load_1.2", 1.2)):
+    for load in loads:
+        tag = "load_%g" % load
         arr = W.poisson_arrivals(len(probs), load * cap, seed=7)
         fin, tts = 0.0, []
         for ta, sv in zip(arr, service):
@@ -409,6 +416,10 @@ def main():
         print("# batching: %s" % out["batching"], file=sys.stderr, flush=True)
         out["serving"] = serving_leg(tlb, torch)
         print("# serving: %s" % out["serving"], file=sys.stderr, flush=True)
+        # the same stream with FP16-deviation storage: capacity and 0.7x load
+        out["serving_fp16dev"] = serving_leg(tlb, torch, precision="fp16dev", loads=(0.7,),
+                                             sequential=False)
+        print("# serving fp16dev: %s" % out["serving_fp16dev"], file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(problem)
     print(json.dumps(out), flush=True)

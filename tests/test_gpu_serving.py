@@ -34,7 +34,7 @@ def solo(tlb, p, precision):
     return s.read_fields()
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16dev"])
 def test_results_identical_alone_and_in_mix(tlb, precision):
     probs = mix()
     # an arena that holds only a few lattices at a time forces queueing and
