@@ -557,11 +557,11 @@ __device__ __forceinline__ Nb32 make_nb32(const Grid& g, int x, int y) {
 // the same wait pattern as every other iteration.
 template <int P>
 __device__ __forceinline__ void pull_f(const Grid& g, const Consts<typename Tr<P>::R>& c,
-                                       const LatView<P>& src, const uint8_t* __restrict__ mat,
+                                       const LatView<P>& src, rsrc_t mat,
                                        int gx, int gy, bool on, typename Tr<P>::R* f1,
                                        typename Tr<P>::R* f2, uint8_t& m) {
     const Nb32 nb = make_nb32(g, gx, gy);
-    m = mat[nb.r0 + nb.x0];
+    m = uint8_t(__builtin_amdgcn_raw_buffer_load_b8(mat, int(nb.r0 + nb.x0), 0, 0));
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
         const unsigned j = nb.up(k);
@@ -794,8 +794,13 @@ __device__ __forceinline__ void step_tile(const Grid& g, const Consts<typename T
     const int lane = threadIdx.x & (kTileX - 1);
     const int w = threadIdx.x / kTileX;
     const LatView<P> src = lat_view<P>(srcb, g.npad);
+    // Every memory access of the step goes through buffer resources or
+    // global-space pointers: a pending generic (flat) load, which might touch
+    // LDS, makes the compiler drain all outstanding loads at every wait.
+    const rsrc_t matr = make_rsrc(mat, unsigned(g.npad));
+    const auto* gmtab = (const __attribute__((address_space(1))) double*)mtab;
     for (int i = threadIdx.x; i < kMatStride * (kMaxMaterials + 1); i += kStepThreads)
-        sm.mt[i] = R(mtab[i]);
+        sm.mt[i] = R(gmtab[i]);
 
     // phase B of iteration it: mu on rows Y+1..Y+4, mu columns 0..65
     auto phase_b = [&](int it) {
@@ -833,10 +838,10 @@ __device__ __forceinline__ void step_tile(const Grid& g, const Consts<typename T
                 sm.c2[sl] = fl ? b : R(0);
                 sm.m[sl] = nm;
             }
-            pull_f<P>(g, c, src, mat, gx, wrapc(Y + 6 + hr, g.ny), act && Y + 6 + hr <= ylast,
+            pull_f<P>(g, c, src, matr, gx, wrapc(Y + 6 + hr, g.ny), act && Y + 6 + hr <= ylast,
                       nf1, nf2, nm);
         };
-        pull_f<P>(g, c, src, mat, gx, wrapc(y0 - 2 + hr, g.ny), act, nf1, nf2, nm);
+        pull_f<P>(g, c, src, matr, gx, wrapc(y0 - 2 + hr, g.ny), act, nf1, nf2, nm);
         halo_a(-1);
         __syncthreads();
         phase_b(-1);
@@ -905,11 +910,11 @@ __device__ __forceinline__ void step_tile(const Grid& g, const Consts<typename T
                     hist, int(gon ? idx * 4u : kDiscard), int(q * hstride), 0));
         }
         __builtin_amdgcn_sched_barrier(0);
-        pull_f<P>(g, c, src, mat, gxl, wrapc(Y + 6 + w, g.ny), Y + 6 + w <= ylast, nf1, nf2, nm);
+        pull_f<P>(g, c, src, matr, gxl, wrapc(Y + 6 + w, g.ny), Y + 6 + w <= ylast, nf1, nf2, nm);
         __builtin_amdgcn_sched_barrier(0);
     };
 
-    pull_f<P>(g, c, src, mat, gxl, wrapc(y0 - 2 + w, g.ny), true, nf1, nf2, nm);
+    pull_f<P>(g, c, src, matr, gxl, wrapc(y0 - 2 + w, g.ny), true, nf1, nf2, nm);
     phase_a(-1);
     __syncthreads();
     phase_b(-1);
