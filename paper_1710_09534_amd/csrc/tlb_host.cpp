@@ -41,7 +41,9 @@ Layout make_layout(int nx, int ny, int prec) {
     Layout L{};
     L.pitch = int(align_up(size_t(nx), kTileX));
     L.npad = size_t(ny) * L.pitch;
-    size_t planes = align_up(27 * L.npad * elem_bytes(prec), kAlign);
+    // FP16-dev: 8 planes of (f^1_k, f^2_k) FP16 pairs and 9 FP16 g planes, then
+    // the two FP32 rest planes
+    size_t planes = align_up((prec == P16 ? 50 : 27 * elem_bytes(prec)) * L.npad, kAlign);
     L.rest_off = planes;
     if (prec == P16) planes += align_up(2 * L.npad * 4, kAlign);
     L.pop_bytes = planes;

@@ -44,12 +44,24 @@ template <> struct Tr<P64> { using R = double; using S = double; using H = doubl
 template <> struct Tr<P32> { using R = float; using S = float; using H = float; };
 template <> struct Tr<P16> { using R = float; using S = _Float16; using H = float; };
 
+// FP16-dev population buffer: f^1_k and f^2_k (k = 1..8) share one 32-bit
+// word (f^1 in the low half) in 8 pair planes, followed by the 9 FP16 g
+// planes; f^1_0 and f^2_0 live in the FP32 rest planes.  Halfword index of
+// population q = 9 f + k (f: f^1, f^2, g) at node i:
+template <int P>
+__device__ __forceinline__ long half_index(int q, long npad, long i) {
+    if (q >= 18) return 16 * npad + (q - 18) * npad + i;
+    const int k = q % 9;
+    return 2 * ((k - 1) * npad + i) + (q / 9);
+}
+
 template <int P>
 __device__ __forceinline__ typename Tr<P>::R ld(const PopBuf& b, const Consts<typename Tr<P>::R>& c,
                                                 int q, long npad, long i) {
     if constexpr (P == P16) {
         if (q == 0 || q == 9) return b.rest[(q / 9) * npad + i];
-        return float(static_cast<const _Float16*>(b.planes)[q * npad + i]) * c.iscale[q / 9];
+        return float(static_cast<const _Float16*>(b.planes)[half_index<P>(q, npad, i)]) *
+               c.iscale[q / 9];
     } else {
         return static_cast<const typename Tr<P>::S*>(b.planes)[q * npad + i];
     }
@@ -62,7 +74,8 @@ __device__ __forceinline__ void st(const PopBuf& b, const Consts<typename Tr<P>:
         if (q == 0 || q == 9) {
             b.rest[(q / 9) * npad + i] = v;
         } else {
-            static_cast<_Float16*>(b.planes)[q * npad + i] = _Float16(v * c.scale[q / 9]);
+            static_cast<_Float16*>(b.planes)[half_index<P>(q, npad, i)] =
+                _Float16(v * c.scale[q / 9]);
         }
     } else {
         static_cast<typename Tr<P>::S*>(b.planes)[q * npad + i] = v;
@@ -418,9 +431,12 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void* p, unsigned bytes) {
 
 template <int P>
 struct LatView {
-    rsrc_t fam[3];      // f^1, f^2, g: plane k of a family at byte offset k * pstride
+    rsrc_t fam[3];      // f^1, f^2, g: plane k of a family at byte offset k * pstride.  P16:
+                        // fam[0], fam[1] hold the (f^1_k, f^2_k) pair planes k = 1..4 and
+                        // 5..8 at offset ((k - 1) & 3) * ppstride, fam[2] the g planes
     rsrc_t rest;        // P16: FP32 rest planes f^1_0 (offset 0), f^2_0 (offset rstride)
     unsigned pstride;   // bytes per plane
+    unsigned ppstride;  // P16 pair-plane bytes
     unsigned rstride;   // P16 rest-plane bytes
 };
 
@@ -430,8 +446,17 @@ __device__ __forceinline__ LatView<P> lat_view(const PopBuf& b, long npad) {
     LatView<P> v;
     const unsigned ps = unsigned(npad * long(sizeof(S)));
     const char* base = static_cast<const char*>(b.planes);
+    if constexpr (P == P16) {
+        const unsigned pp = unsigned(npad * 4);
+        v.fam[0] = make_rsrc(base, 4u * pp);
+        v.fam[1] = make_rsrc(base + long(4) * pp, 4u * pp);
+        v.fam[2] = make_rsrc(base + long(8) * pp, 9u * ps);
+        v.ppstride = pp;
+    } else {
 #pragma unroll
-    for (int f = 0; f < 3; ++f) v.fam[f] = make_rsrc(base + long(f) * 9 * ps, 9u * ps);
+        for (int f = 0; f < 3; ++f) v.fam[f] = make_rsrc(base + long(f) * 9 * ps, 9u * ps);
+        v.ppstride = 0;
+    }
     v.pstride = ps;
     v.rstride = unsigned(npad * 4);
     v.rest = make_rsrc(P == P16 ? static_cast<const void*>(b.rest) : static_cast<const void*>(base),
@@ -468,6 +493,8 @@ __device__ __forceinline__ typename Tr<P>::R bld(const LatView<P>& v,
                                                           int(k * v.pstride), 0);
         return __builtin_bit_cast(float, r);
     } else {
+        // f^1_0, f^2_0 from the rest planes and g here; the f^1, f^2 pairs of
+        // k >= 1 are loaded together by bld12
         if (k == 0 && f < 2) {
             unsigned r = __builtin_amdgcn_raw_buffer_load_b32(v.rest, int(on ? j * 4u : kDiscard),
                                                               int(f * v.rstride), 0);
@@ -493,6 +520,8 @@ __device__ __forceinline__ void bst(const LatView<P>& v, const Consts<typename T
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), v.fam[f], int(ob),
                                               int(k * v.pstride), Policy<P>::kStore);
     } else {
+        // f^1_0, f^2_0 to the rest planes and g here; f^1, f^2 pairs of k >= 1
+        // go through bst12
         if (k == 0 && f < 2) {
             __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), v.rest,
                                                   int(orb), int(f * v.rstride), Policy<P>::kStore);
@@ -502,6 +531,46 @@ __device__ __forceinline__ void bst(const LatView<P>& v, const Consts<typename T
         __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h), v.fam[f],
                                               int(ob), int(k * v.pstride), Policy<P>::kStore);
     }
+}
+
+// f^1_k and f^2_k at node j together: one load of the pair word in P16
+template <int P>
+__device__ __forceinline__ void bld12(const LatView<P>& v, const Consts<typename Tr<P>::R>& c,
+                                      int k, unsigned j, bool on, typename Tr<P>::R& x1,
+                                      typename Tr<P>::R& x2) {
+    if constexpr (P == P16) {
+        if (k > 0) {
+            const unsigned r = __builtin_amdgcn_raw_buffer_load_b32(
+                v.fam[(k - 1) >> 2], int(on ? j * 4u : kDiscard),
+                int(unsigned((k - 1) & 3) * v.ppstride), 0);
+            x1 = float(__builtin_bit_cast(_Float16, (unsigned short)(r & 0xffffu))) * c.iscale[0];
+            x2 = float(__builtin_bit_cast(_Float16, (unsigned short)(r >> 16))) * c.iscale[1];
+            return;
+        }
+    }
+    x1 = bld<P>(v, c, 0, k, j, on);
+    x2 = bld<P>(v, c, 1, k, j, on);
+}
+
+// store f^1_k and f^2_k of one node (byte offsets ob of an S element, o4 of a
+// 4-byte element): one store of the pair word in P16
+template <int P>
+__device__ __forceinline__ void bst12(const LatView<P>& v, const Consts<typename Tr<P>::R>& c,
+                                      int k, unsigned ob, unsigned o4, typename Tr<P>::R x1,
+                                      typename Tr<P>::R x2) {
+    if constexpr (P == P16) {
+        if (k > 0) {
+            const _Float16 h1 = _Float16(x1 * c.scale[0]), h2 = _Float16(x2 * c.scale[1]);
+            const unsigned w = unsigned(__builtin_bit_cast(unsigned short, h1)) |
+                               (unsigned(__builtin_bit_cast(unsigned short, h2)) << 16);
+            __builtin_amdgcn_raw_buffer_store_b32(w, v.fam[(k - 1) >> 2], int(o4),
+                                                  int(unsigned((k - 1) & 3) * v.ppstride),
+                                                  Policy<P>::kStore);
+            return;
+        }
+    }
+    bst<P>(v, c, 0, k, ob, o4, x1);
+    bst<P>(v, c, 1, k, ob, o4, x2);
 }
 
 template <int P>
@@ -563,11 +632,7 @@ __device__ __forceinline__ void pull_f(const Grid& g, const Consts<typename Tr<P
     const Nb32 nb = make_nb32(g, gx, gy);
     m = uint8_t(__builtin_amdgcn_raw_buffer_load_b8(mat, int(nb.r0 + nb.x0), 0, 0));
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        const unsigned j = nb.up(k);
-        f1[k] = bld<P>(src, c, 0, k, j, on);
-        f2[k] = bld<P>(src, c, 1, k, j, on);
-    }
+    for (int k = 0; k < 9; ++k) bld12<P>(src, c, k, nb.up(k), on, f1[k], f2[k]);
 }
 
 // Chemical potentials of one mu-ring node (mu column mcol, c column
@@ -728,8 +793,7 @@ __device__ __forceinline__ void node_update(const Grid& g, const Consts<typename
                 const R gu = omg * (gg[k] + o.rho * (skw - sku)) +
                              w * (Pg + R(3) * (fsg * (eF - wF) + o.am * ew)) +
                              skw * (Rg + fsg * (eA - wA));
-                bst<P>(dst, c, 0, k, sb, s4, f1u);
-                bst<P>(dst, c, 1, k, sb, s4, f2u);
+                bst12<P>(dst, c, k, sb, s4, f1u, f2u);
                 bst<P>(dst, c, 2, k, sb, s4, gu);
             }
         }
@@ -753,8 +817,7 @@ __device__ __forceinline__ void node_update(const Grid& g, const Consts<typename
             f2[k] = om2 * f2[k] + w * (P2 + eV2);
             g2[k] = omg * gg[k] + w * (Pg + eG - G0) + sk * (Rg + fsg * (eA - uA));
         }
-        bst<P>(dst, c, 0, k, ob, o4, f1[k]);
-        bst<P>(dst, c, 1, k, ob, o4, f2[k]);
+        bst12<P>(dst, c, k, ob, o4, f1[k], f2[k]);
         bst<P>(dst, c, 2, k, ob, o4, g2[k]);
     }
     if (live && (mask & kWallBits)) {
@@ -766,8 +829,7 @@ __device__ __forceinline__ void node_update(const Grid& g, const Consts<typename
                 const R corr = -R(6) * wgt<R>(k) * (R(EX[k]) * tm[3] + R(EY[k]) * tm[4]);
                 const unsigned sn = nb.dn(k);
                 const unsigned sb = sn * unsigned(sizeof(typename Tr<P>::S)), s4 = sn * 4u;
-                bst<P>(dst, c, 0, OPP[k], sb, s4, f1[k] + corr * o.c1);
-                bst<P>(dst, c, 1, OPP[k], sb, s4, f2[k] + corr * o.c2);
+                bst12<P>(dst, c, OPP[k], sb, s4, f1[k] + corr * o.c1, f2[k] + corr * o.c2);
                 bst<P>(dst, c, 2, OPP[k], sb, s4, g2[k] + corr * o.rho);
             }
         }

@@ -159,15 +159,13 @@ def test_size_limit_boundary(prec, nx, elem, hist):
 
 def test_workspace_is_lattice_plus_modest_staging():
     """The staging area holds the 4 init fields, not a full copy of the
-    populations: workspace bytes per node stay close to the lattice's own
-    (FP16-dev also keeps the unused FP16 slots of the two rest planes, whose
-    values live in FP32 planes: 8 bytes per node)."""
+    populations: workspace bytes per node stay close to the lattice's own."""
     from paper_1710_09534_amd import tlb
     n = 1024 * 2048
     for prec, lattice in ((0, 2 * 27 * 8 + 4 * 8 + 1), (1, 2 * 27 * 4 + 4 * 4 + 1),
                           (2, 2 * (25 * 2 + 2 * 4) + 4 * 4 + 1)):
         per_node = tlb.tlb_workspace_bytes(1024, 2048, prec) / n
-        assert lattice <= per_node <= lattice + 4 * 8 + 8 + 1, (prec, per_node)
+        assert lattice <= per_node <= lattice + 4 * 8 + 1, (prec, per_node)
 
 
 def test_size_limit_boundary_3d():
