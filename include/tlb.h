@@ -280,6 +280,9 @@ tlb_status tlb_server_release(tlb_server* s, uint64_t id);
 /* queued: dropped; running: leaves at the next quantum boundary */
 tlb_status tlb_server_cancel(tlb_server* s, uint64_t id);
 tlb_status tlb_server_stats(tlb_server* s, tlb_server_counters* out);
+/* Message of the calling thread's last failed tlb_server_* call (valid until
+ * that thread's next server call; s may be NULL).  A failed request's own
+ * reason is returned by tlb_server_result. */
 const char* tlb_server_last_error(const tlb_server* s);
 /* stops the worker (running and queued requests are cancelled) */
 void       tlb_server_destroy(tlb_server* s);

@@ -122,7 +122,6 @@ struct tlb_server {
     uint64_t next_id = 1;
     bool stop = false;
     std::thread worker;
-    std::string err;
     // statistics
     double busy_s = 0.0;
     double node_steps = 0.0;
@@ -131,10 +130,12 @@ struct tlb_server {
 
 namespace {
 
+// message of the calling thread's last failed server call (a per-server
+// string would be written by concurrent callers and the worker at once);
+// failures inside the worker are reported per request
 thread_local std::string g_server_error;
 
-tlb_status sfail(tlb_server* s, tlb_status st, const std::string& m) {
-    if (s) s->err = m;
+tlb_status sfail(tlb_server*, tlb_status st, const std::string& m) {
     g_server_error = m;
     return st;
 }
@@ -278,11 +279,11 @@ void worker_loop(tlb_server* s) {
             for (auto& r : run) ctxs.push_back(r->ctx);
             if (tlb_batch_set(s->batch, ctxs.data(), int(ctxs.size())) != TLB_OK) {
                 std::lock_guard<std::mutex> lk(s->mu);
-                s->err = tlb_batch_last_error(s->batch);
+                const std::string why = tlb_batch_last_error(s->batch);
                 for (auto& r : run) {
                     release_request(s, *r);
                     r->state = TLB_REQ_FAILED;
-                    r->error = s->err;
+                    r->error = why;
                     r->done = Clock::now();
                     ++s->failed;
                 }
@@ -500,9 +501,7 @@ tlb_status tlb_server_stats(tlb_server* s, tlb_server_counters* out) {
     return TLB_OK;
 }
 
-const char* tlb_server_last_error(const tlb_server* s) {
-    return s ? s->err.c_str() : g_server_error.c_str();
-}
+const char* tlb_server_last_error(const tlb_server*) { return g_server_error.c_str(); }
 
 void tlb_server_destroy(tlb_server* s) {
     if (!s) return;
