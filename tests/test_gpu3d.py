@@ -55,7 +55,9 @@ def test_init_state_matches_3d(tlb):
 
 
 @pytest.mark.parametrize("geometry,nx,ny,nz", [
-    ("channel", 70, 20, 14), ("sphere", 40, 30, 26), ("box", 36, 18, 12), ("periodic", 66, 9, 10)])
+    ("channel", 70, 20, 14), ("sphere", 40, 30, 26), ("box", 36, 18, 12), ("periodic", 66, 9, 10),
+    # several z-chunks of the step kernel, walls inside a short last chunk
+    ("channel", 70, 20, 40), ("box", 40, 12, 40), ("sphere", 40, 30, 70)])
 def test_random_three_phase_3d(tlb, geometry, nx, ny, nz):
     p = W.random_fields3(nx, ny, nz, geometry=geometry, U=0.01, rho=(3.0, 2.0, 1.0),
                          gravity=(0.0, 0.0, -1e-6))
