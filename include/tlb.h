@@ -189,7 +189,8 @@ tlb_status tlb_time_steps(tlb_ctx* ctx, int64_t nsteps, double* ms_per_step);
 /* Rows of the strip one workgroup of the step kernel marches through
  * (tuning knob; results are bitwise identical for every legal value).
  * rows: a multiple of 4 in [8, 4096].  Default, with C the device's compute
- * units and W = 2 resident step workgroups per CU (1 in FP64): 128 when
+ * units and W = 2 strips per CU (1 in FP64), the count that measured
+ * fastest: 128 when
  * strips of 64 rows would outnumber C * W but strips of 128 rows would not;
  * else 64 when that gives at least C strips; else the tallest of 48, 32, 24
  * that does, or 16. */
@@ -272,7 +273,10 @@ tlb_status tlb_server_poll(tlb_server* s, uint64_t id, int* state);
 /* blocks until the request is DONE, FAILED or CANCELLED (timeout_s < 0:
  * no limit; TLB_EBUSY on timeout) */
 tlb_status tlb_server_wait(tlb_server* s, uint64_t id, double timeout_s);
-/* fields (bit order, subset of result_fields) and time to solution */
+/* fields (bit order, subset of result_fields) and time to solution.  A
+ * FAILED request returns the status that failed it: TLB_EDIVERGED for a
+ * NaN/Inf order parameter, TLB_EPARAM / TLB_EINVAL for a fluid or geometry
+ * that tlb_create / tlb_set_geometry reject, TLB_EDEVICE for a HIP error. */
 tlb_status tlb_server_result(tlb_server* s, uint64_t id, uint32_t field_mask,
                              double* host_out, double* latency_s);
 /* forgets a finished request (frees its host result) */

@@ -46,7 +46,6 @@ Layout3 make_layout3(int nx, int ny, int nz, int prec) {
     L.off_muf = o; o += align_up(3 * L.npad * s, kAlign);
     L.off_mat = o; o += align_up(L.npad, kAlign);
     L.off_mtab = o; o += align_up(kMatStride * (kMaxMaterials + 1) * sizeof(double), kAlign);
-    // staging: inputs of init (5 fields), readout (11), one population family (19)
     // staging: the 5 input fields of init; readout and population copies pass
     // through it in bands of z-planes (at least one plane of 19 populations)
     L.stage_doubles = std::max(5 * L.n, size_t(kQ) * nx * ny);

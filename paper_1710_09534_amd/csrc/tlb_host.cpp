@@ -152,15 +152,13 @@ void fill_consts(Consts<R>& k, const tlb_ctx* c) {
     k.nee = 0u;
 }
 
-// Default strip height: 64 rows, or the tallest of 48, 32, 24, 16 that still
-// gives the lattice one strip per compute unit (a lone small lattice
-// otherwise runs as a few workgroups each marching 64 rows in sequence).
-// Default strip height.  A lattice that gives every workgroup slot of the
-// device a strip of 64 rows uses 64, or 128 when 128 fits all strips into
-// one round of resident workgroups and 64 does not (measured: FP64 at
-// 1024 x 2048 and FP32 at 2048 x 2048 run faster with one round of taller
-// strips than two rounds of 64-row ones).  Resident step workgroups per CU:
-// two in FP32 and FP16-dev (5 waves of 128 VGPRs), one in FP64 (224 VGPRs).
+// Default strip height.  W strips per CU keep a CU busiest: two in FP32 and
+// FP16-dev, one in FP64.  (FP64 waves take about 230 VGPRs, so one 5-wave
+// workgroup fits a CU; FP32 and FP16-dev take 128, so three fit, but a third
+// strip per CU measured no faster.)  A lattice that gives every CU at least
+// that many strips of 64 rows uses 64, or 128 when 128-row strips number at
+// most W per CU and 64-row ones more (measured: FP64 at 1024 x 2048 and FP32
+// at 2048 x 2048 run faster as one round of taller strips).
 // Smaller lattices take the tallest of 48, 32, 24, 16 rows that still gives
 // one strip per CU, so that a lone small lattice is not marched by a few
 // workgroups.
@@ -587,7 +585,10 @@ tlb_status tlb_mass(tlb_ctx* c, double out[3]) {
 }
 
 tlb_status tlb_checkpoint_bytes(const tlb_ctx* c, size_t* bytes) {
-    if (!c || !bytes) return TLB_EINVAL;
+    if (!c || !bytes) {
+        g_last_error = "null pointer";
+        return TLB_EINVAL;
+    }
     *bytes = 64 + c->L.pop_bytes + c->L.hist_bytes;
     return TLB_OK;
 }

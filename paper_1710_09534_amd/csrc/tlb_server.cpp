@@ -93,6 +93,7 @@ struct Request {
     uint32_t keep;
     int state = TLB_REQ_QUEUED;
     bool cancel = false;
+    tlb_status status = TLB_OK;   // what failed a FAILED request
     std::string error;
     Clock::time_point arrival, done;
     size_t ws_off = 0, ws_bytes = 0;
@@ -161,7 +162,9 @@ bool start_request(tlb_server* s, Request& r) {
     // strips for small lattices would only add halo work
     if (st == TLB_OK) st = tlb_set_tile_rows(r.ctx, 64);
     if (st != TLB_OK) {
+        // with r.ctx NULL (tlb_create failed) this is the thread's last message
         r.error = tlb_last_error(r.ctx);
+        r.status = st;
         return false;
     }
     // the host copies of the inputs are no longer needed
@@ -179,6 +182,7 @@ bool finish_request(tlb_server* s, Request& r) {
     tlb_status st = tlb_mass(r.ctx, m);
     if (st != TLB_OK) {
         r.error = st == TLB_EDIVERGED ? "diverged (NaN/Inf order parameter)" : tlb_last_error(r.ctx);
+        r.status = st;
         return false;
     }
     const size_t n = size_t(r.nx) * r.ny;
@@ -187,6 +191,7 @@ bool finish_request(tlb_server* s, Request& r) {
         st = tlb_read_fields(r.ctx, r.keep, r.result.data());
         if (st != TLB_OK) {
             r.error = tlb_last_error(r.ctx);
+            r.status = st;
             return false;
         }
     }
@@ -241,7 +246,10 @@ void worker_loop(tlb_server* s) {
             }
         }
         for (auto& rp : admitted) {
-            if (!dev_ok) rp->error = "hipSetDevice failed on the server thread";
+            if (!dev_ok) {
+                rp->error = "hipSetDevice failed on the server thread";
+                rp->status = TLB_EDEVICE;
+            }
             if (dev_ok && start_request(s, *rp)) {
                 std::lock_guard<std::mutex> lk(s->mu);
                 s->running.push_back(rp);
@@ -277,12 +285,14 @@ void worker_loop(tlb_server* s) {
         if (composition_changed) {
             std::vector<tlb_ctx*> ctxs;
             for (auto& r : run) ctxs.push_back(r->ctx);
-            if (tlb_batch_set(s->batch, ctxs.data(), int(ctxs.size())) != TLB_OK) {
+            const tlb_status bst = tlb_batch_set(s->batch, ctxs.data(), int(ctxs.size()));
+            if (bst != TLB_OK) {
                 std::lock_guard<std::mutex> lk(s->mu);
                 const std::string why = tlb_batch_last_error(s->batch);
                 for (auto& r : run) {
                     release_request(s, *r);
                     r->state = TLB_REQ_FAILED;
+                    r->status = bst;
                     r->error = why;
                     r->done = Clock::now();
                     ++s->failed;
@@ -319,6 +329,7 @@ void worker_loop(tlb_server* s) {
             release_request(s, *r);
             r->done = Clock::now();
             r->state = ok ? TLB_REQ_DONE : TLB_REQ_FAILED;
+            if (!ok && st != TLB_OK) r->status = st;
             if (!ok && r->error.empty()) r->error = tlb_batch_last_error(s->batch);
             if (ok) ++s->completed;
             else ++s->failed;
@@ -329,12 +340,17 @@ void worker_loop(tlb_server* s) {
     }
     // shutdown: release everything still held
     std::lock_guard<std::mutex> lk(s->mu);
+    const auto now = Clock::now();
     for (auto& r : s->running) {
         release_request(s, *r);
         r->state = TLB_REQ_CANCELLED;
+        r->done = now;
     }
     s->running.clear();
-    for (auto& r : s->queue) r->state = TLB_REQ_CANCELLED;
+    for (auto& r : s->queue) {
+        r->state = TLB_REQ_CANCELLED;
+        r->done = now;
+    }
     s->queue.clear();
     s->cv_done.notify_all();
 }
@@ -444,7 +460,8 @@ tlb_status tlb_server_result(tlb_server* s, uint64_t id, uint32_t mask, double* 
     auto it = s->all.find(id);
     if (it == s->all.end()) return sfail(s, TLB_EINVAL, "unknown request id");
     Request& r = *it->second;
-    if (r.state == TLB_REQ_FAILED) return sfail(s, TLB_EDIVERGED, "request failed: " + r.error);
+    if (r.state == TLB_REQ_FAILED)
+        return sfail(s, r.status != TLB_OK ? r.status : TLB_EDEVICE, "request failed: " + r.error);
     if (r.state == TLB_REQ_CANCELLED) return sfail(s, TLB_ESTATE, "request was cancelled");
     if (r.state != TLB_REQ_DONE) return sfail(s, TLB_EBUSY, "request not finished");
     if (latency_s) *latency_s = std::chrono::duration<double>(r.done - r.arrival).count();

@@ -268,6 +268,11 @@ class Solver:
         return buf.raw
 
     def checkpoint_load(self, blob: bytes):
+        n = C.c_size_t()
+        _check(lib.tlb_checkpoint_bytes(self.ctx, C.byref(n)), self.ctx)
+        if len(blob) != n.value:   # the library reads exactly that many bytes
+            raise ValueError("checkpoint of %d bytes for a context that takes %d"
+                             % (len(blob), n.value))
         buf = C.create_string_buffer(blob, len(blob))
         _check(lib.tlb_checkpoint_load(self.ctx, buf), self.ctx)
 
@@ -474,7 +479,8 @@ class Server:
             if a is None:
                 return None
             a = np.ascontiguousarray(a, dtype=dtype)
-            assert a.shape == (ny, nx)
+            if a.shape != (ny, nx):
+                raise ValueError("array of shape %s for a %d x %d lattice" % (a.shape, nx, ny))
             keep.append(a)
             return a
 

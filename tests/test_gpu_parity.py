@@ -152,6 +152,8 @@ def test_checkpoint_roundtrip_bitwise(tlb):
     blob = a.checkpoint_save()
     a.step(60)
     b = tlb.from_problem(p, init=False)
+    with pytest.raises(ValueError):
+        b.checkpoint_load(blob[:-8])      # truncated: refused before the library reads it
     b.checkpoint_load(blob)
     assert b.step_count == 40
     b.step(60)

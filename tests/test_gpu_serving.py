@@ -68,16 +68,26 @@ def test_cancel_and_failure_isolation(tlb):
     probs = mix(3)
     bad = dict(probs[1])
     bad["fluid"] = dict(bad["fluid"], gravity=[0.0, -50.0])  # diverges
+    inadmissible = dict(probs[1])
+    inadmissible["fluid"] = dict(inadmissible["fluid"], tau1=0.4)  # tau_i <= 1/2
     srv = tlb.Server(1 << 30, max_slots=4, precision="fp64", quantum=50)
     ok_id = srv.submit(probs[0], 300)
     bad_id = srv.submit(bad, 400)
+    rej_id = srv.submit(inadmissible, 100)
     long_id = srv.submit(probs[2], 10 ** 7)
     srv.wait(ok_id, 120.0)
     srv.wait(bad_id, 120.0)
+    srv.wait(rej_id, 120.0)
     assert srv.poll(ok_id) == tlb.TLB_REQ_DONE
     assert srv.poll(bad_id) == tlb.TLB_REQ_FAILED
-    with pytest.raises(tlb.TlbError):
+    assert srv.poll(rej_id) == tlb.TLB_REQ_FAILED
+    # each failed request reports what failed it
+    with pytest.raises(tlb.TlbError) as e:
         srv.result(bad_id, bad["nx"], bad["ny"])
+    assert e.value.status == tlb.TLB_EDIVERGED
+    with pytest.raises(tlb.TlbError) as e:
+        srv.result(rej_id, bad["nx"], bad["ny"])
+    assert e.value.status == tlb.TLB_EPARAM and "tau" in str(e.value)
     srv.cancel(long_id)
     srv.wait(long_id, 120.0)
     assert srv.poll(long_id) == tlb.TLB_REQ_CANCELLED
