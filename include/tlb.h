@@ -20,9 +20,11 @@
  *  - Every call returns a tlb_status (0 = TLB_OK); nothing throws across the
  *    ABI.  Errors are checked in the order EINVAL (null pointer, bad size),
  *    EPARAM (inadmissible physics), ESTATE (call order), EDIVERGED, EDEVICE.
- *    A failed call leaves the context unchanged, except EDIVERGED, after
- *    which only read_fields, read_populations, checkpoint_save, mass and
- *    destroy are allowed.  tlb_last_error() gives the message.
+ *    A failed call leaves the context unchanged, except EDIVERGED: after it
+ *    tlb_step keeps returning EDIVERGED (and a batch refuses the context)
+ *    until tlb_init_fields or tlb_checkpoint_load replaces the state; reads,
+ *    mass, checkpoint_save and destroy still work.  tlb_last_error() gives
+ *    the message.
  *  - Host arrays are borrowed for the duration of the call only.
  *  - A context is not thread-safe.  Contexts on different streams may run
  *    concurrently.

@@ -190,6 +190,16 @@ def test_divergence_is_reported(tlb):
             g.step(10)
             g.mass()
     assert e.value.status == tlb.TLB_EDIVERGED
-    with pytest.raises(tlb.TlbError):
+    with pytest.raises(tlb.TlbError) as e:
         g.step(1)
+    assert e.value.status == tlb.TLB_EDIVERGED
     g.read_fields()  # still allowed
+    # a batch refuses the diverged context
+    b = tlb.Batch(2)
+    with pytest.raises(tlb.TlbError) as e:
+        b.set([g])
+    assert e.value.status == tlb.TLB_EDIVERGED
+    # new initial fields replace the state and clear the flag
+    g.init_fields(p["c1"], p["c2"])
+    g.step(1)
+    assert np.all(np.isfinite(g.mass()))
