@@ -283,22 +283,49 @@ def serving_leg(tlb, torch, precision="fp32", n_requests=120, steps=(1000, 4000)
     return out
 
 
-def cpu_baseline(problem, budget_s=12.0):
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_rate(problem, budget_s, max_steps):
+    """MLUPS of the FP64 oracle on `problem`: one untimed step, then as many
+    steps as fit the budget (at most max_steps)."""
     import oracle
     o = oracle.Oracle(problem)
     o.init(problem["c1"], problem["c2"], problem["ux"], problem["uy"])
     t0 = time.perf_counter()
     o.step(1)
     one = time.perf_counter() - t0
-    k = max(1, min(50, int(budget_s / max(one, 1e-3))))
+    k = max(1, min(max_steps, int(budget_s / max(one, 1e-3))))
     t0 = time.perf_counter()
     o.step(k)
     dt = time.perf_counter() - t0
-    n = problem["nx"] * problem["ny"]
-    return {"value": round(n * k / dt / 1e6, 3), "unit": "MLUPS", "cores": oracle.Oracle.num_threads(),
+    del o
+    return problem["nx"] * problem["ny"] * k / dt / 1e6, k
+
+
+def cpu_baseline(problem, budget_s=12.0, single_budget_s=6.0):
+    import oracle
+    cores = oracle.Oracle.num_threads()
+    rate, k = oracle_rate(problem, budget_s, 50)
+    oracle.Oracle.set_num_threads(1)
+    try:
+        rate1, k1 = oracle_rate(problem, single_budget_s, 20)
+    finally:
+        oracle.Oracle.set_num_threads(cores)
+    return {"value": round(rate, 3), "unit": "MLUPS", "cores": cores,
             "kind": "oracle",
             "sample": "%d steps of the %dx%d workload (after 1 untimed step), FP64 oracle"
-                      % (k, problem["nx"], problem["ny"])}
+                      % (k, problem["nx"], problem["ny"]),
+            "single_thread": {"value": round(rate1, 3), "unit": "MLUPS",
+                              "sample": "%d steps, 1 thread" % k1},
+            "cpu_model": cpu_model()}
 
 
 def main():

@@ -300,6 +300,11 @@ class Oracle:
     def num_threads() -> int:
         return _load().orc_num_threads()
 
+    @staticmethod
+    def set_num_threads(n: int) -> None:
+        """Threads of the calling thread's later oracle calls."""
+        _load().orc_set_num_threads(int(n))
+
 
 # ------------------------------------------------------------------ 3-D
 FIELDS3 = ("c1", "c2", "c3", "rho", "ux", "uy", "uz", "p", "mu1", "mu2", "mu3")
