@@ -153,7 +153,7 @@ void fill_consts(Consts<R>& k, const tlb_ctx* c) {
 }
 
 // Default strip height.  W strips per CU keep a CU busiest: two in FP32 and
-// FP16-dev, one in FP64.  (FP64 waves take about 230 VGPRs, so one 5-wave
+// FP16-dev, one in FP64.  (FP64 waves take about 245 VGPRs, so one 5-wave
 // workgroup fits a CU; FP32 and FP16-dev take 128, so three fit, but a third
 // strip per CU measured no faster.)  A lattice that gives every CU at least
 // that many strips of 64 rows uses 64, or 128 when 128-row strips number at

@@ -924,70 +924,75 @@ __device__ __forceinline__ void step_tile(const Grid& g, const Consts<typename T
     const LatView<P> dst = lat_view<P>(dstb, g.npad);
     const unsigned hstride = unsigned(g.npad * long(sizeof(HT)));
     const rsrc_t hist = make_rsrc(histp, 4u * hstride);
-    R cf1[9], cf2[9], gg[9], ho[4];
-    Nb32 nb;
-    unsigned idx = 0;
-    int yo = 0;
+    if constexpr (P == P64) {
+        // Two register sets of pulled populations alternate (the loop is
+        // unrolled by two): phase A of iteration it consumes the set pulled
+        // one iteration earlier (u) and pulls the next row into the other
+        // (f); phase C of iteration it uses u.  With one set carried around
+        // the loop (the FP32 / FP16-dev code below), the FP64 kernel kept the
+        // consumed copy in the loop-carried registers and moved the new pulls
+        // into them at the back edge, which waits for every pull before the
+        // barrier: 228 us per step against 215 us with two sets.  In FP32 and
+        // FP16-dev a second set does not fit the 128-VGPR budget (spills;
+        // FP32 111 -> 152 us), and the two-set source compiled to a 3 %
+        // slower FP32 kernel even with the copy, so they keep the code below.
+        R fb1[9], fb2[9], gg[9], ho[4];
+        uint8_t mb;
+        Nb32 nb;
+        unsigned idx = 0;
+        int yo = 0;
 
-    // phase A of iteration it: c of row Y+2+w from the prefetched pulls, then
-    // the phase-C operands of iteration it, then the pulls for iteration it+1
-    auto phase_a = [&](int it) {
-        const int Y = y0 + 4 * it;
-        const int sl = ring_slot(Y + 2 + w, y0) * RG::W + lane + 2;
-        R a = R(0), b = R(0);
-#pragma unroll
-        for (int k = 0; k < 9; ++k) {
-            cf1[k] = nf1[k];
-            cf2[k] = nf2[k];
-            a += cf1[k];
-            b += cf2[k];
-        }
-        const bool fl = nm == 0;
-        sm.c1[sl] = fl ? a : R(0);
-        sm.c2[sl] = fl ? b : R(0);
-        sm.m[sl] = nm;
-        if (w >= 2) {
+        // phase A of iteration it: c of row Y+2+w from the prefetched pulls u,
+        // then the phase-C operands of iteration it, then the pulls for
+        // iteration it+1 into f
+        auto phase_a = [&](int it, const R (&u1)[9], const R (&u2)[9], uint8_t um, R (&f1)[9],
+                           R (&f2)[9], uint8_t& fm) {
+            const int Y = y0 + 4 * it;
+            const int sl = ring_slot(Y + 2 + w, y0) * RG::W + lane + 2;
+            R a = R(0), b = R(0);
 #pragma unroll
             for (int k = 0; k < 9; ++k) {
-                sm.stash[it & 1][w - 2][k][lane] = cf1[k];
-                sm.stash[it & 1][w - 2][9 + k][lane] = cf2[k];
+                a += u1[k];
+                b += u2[k];
             }
-        }
-        // issued on every path before the next row's pulls so that waiting
-        // for them leaves those in flight; rows outside the strip load out of
-        // range (no traffic)
-        yo = Y + ((w + 2) & 3);
-        nb = make_nb32(g, gxl, wrapc(yo, g.ny));
-        idx = nb.r0 + nb.x0;
-        const bool gon = yo >= y0 && yo < y0 + rows;
+            const bool fl = um == 0;
+            sm.c1[sl] = fl ? a : R(0);
+            sm.c2[sl] = fl ? b : R(0);
+            sm.m[sl] = um;
+            if (w >= 2) {
 #pragma unroll
-        for (int k = 0; k < 9; ++k) gg[k] = bld<P>(src, c, 2, k, nb.up(k), gon);
+                for (int k = 0; k < 9; ++k) {
+                    sm.stash[it & 1][w - 2][k][lane] = u1[k];
+                    sm.stash[it & 1][w - 2][9 + k][lane] = u2[k];
+                }
+            }
+            // issued on every path before the next row's pulls so that waiting
+            // for them leaves those in flight; rows outside the strip load out of
+            // range (no traffic)
+            yo = Y + ((w + 2) & 3);
+            nb = make_nb32(g, gxl, wrapc(yo, g.ny));
+            idx = nb.r0 + nb.x0;
+            const bool gon = yo >= y0 && yo < y0 + rows;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            if constexpr (P == P64)
-                ho[q] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
-                    hist, int(gon ? idx * 8u : kDiscard), int(q * hstride), 0));
-            else
-                ho[q] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
-                    hist, int(gon ? idx * 4u : kDiscard), int(q * hstride), 0));
-        }
-        __builtin_amdgcn_sched_barrier(0);
-        pull_f<P>(g, c, src, matr, gxl, wrapc(Y + 6 + w, g.ny), Y + 6 + w <= ylast, nf1, nf2, nm);
-        __builtin_amdgcn_sched_barrier(0);
-    };
+            for (int k = 0; k < 9; ++k) gg[k] = bld<P>(src, c, 2, k, nb.up(k), gon);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if constexpr (P == P64)
+                    ho[q] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+                        hist, int(gon ? idx * 8u : kDiscard), int(q * hstride), 0));
+                else
+                    ho[q] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                        hist, int(gon ? idx * 4u : kDiscard), int(q * hstride), 0));
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            pull_f<P>(g, c, src, matr, gxl, wrapc(Y + 6 + w, g.ny), Y + 6 + w <= ylast, f1, f2, fm);
+            __builtin_amdgcn_sched_barrier(0);
+        };
 
-    pull_f<P>(g, c, src, matr, gxl, wrapc(y0 - 2 + w, g.ny), true, nf1, nf2, nm);
-    phase_a(-1);
-    __syncthreads();
-    phase_b(-1);
-    __syncthreads();
-    phase_a(0);
-    for (int it = 0; it < nit; ++it) {
-        __syncthreads();
-        phase_b(it);
-        __syncthreads();
-        // ---- phase C
-        {
+        // phase C of iteration it: row wave w updates row yo from u (waves 0, 1)
+        // or from the row it parked in the stash one iteration earlier (waves 2,
+        // 3, loaded into u, which phase A no longer needs)
+        auto phase_c = [&](int it, R (&u1)[9], R (&u2)[9]) {
             Stencil<R> s;
             const int sl[3] = {ring_slot(yo - 1, y0), ring_slot(yo, y0), ring_slot(yo + 1, y0)};
             const int ml[3] = {mu_slot(yo - 1, y0), mu_slot(yo, y0), mu_slot(yo + 1, y0)};
@@ -1005,16 +1010,128 @@ __device__ __forceinline__ void step_tile(const Grid& g, const Consts<typename T
             if (w >= 2) {
 #pragma unroll
                 for (int k = 0; k < 9; ++k) {
-                    cf1[k] = sm.stash[(it - 1) & 1][w - 2][k][lane];
-                    cf2[k] = sm.stash[(it - 1) & 1][w - 2][9 + k][lane];
+                    u1[k] = sm.stash[(it - 1) & 1][w - 2][k][lane];
+                    u2[k] = sm.stash[(it - 1) & 1][w - 2][9 + k][lane];
                 }
             }
-            node_update<P, F>(g, c, s, sm.mt, nb, idx, live, mask, cf1, cf2, gg, ho, dst, hist,
-                              hstride);
+            node_update<P, F>(g, c, s, sm.mt, nb, idx, live, mask, u1, u2, gg, ho, dst, hist, hstride);
+        };
+
+        pull_f<P>(g, c, src, matr, gxl, wrapc(y0 - 2 + w, g.ny), true, nf1, nf2, nm);
+        // sets A (nf) and B (fb) alternate
+        phase_a(-1, nf1, nf2, nm, fb1, fb2, mb);
+        __syncthreads();
+        phase_b(-1);
+        __syncthreads();
+        phase_a(0, fb1, fb2, mb, nf1, nf2, nm);
+        for (int it = 0; it < nit; it += 2) {
+            __syncthreads();
+            phase_b(it);
+            __syncthreads();
+            phase_c(it, fb1, fb2);
+            // phase A of the next iteration (after the last one its loads
+            // are all out of range)
+            phase_a(it + 1, nf1, nf2, nm, fb1, fb2, mb);
+            if (it + 1 == nit) break;
+            __syncthreads();
+            phase_b(it + 1);
+            __syncthreads();
+            phase_c(it + 1, nf1, nf2);
+            phase_a(it + 2, fb1, fb2, mb, nf1, nf2, nm);
         }
-        // phase A of the next iteration (after the last one its loads are
-        // all out of range)
-        phase_a(it + 1);
+    } else {
+        R cf1[9], cf2[9], gg[9], ho[4];
+        Nb32 nb;
+        unsigned idx = 0;
+        int yo = 0;
+
+        // phase A of iteration it: c of row Y+2+w from the prefetched pulls, then
+        // the phase-C operands of iteration it, then the pulls for iteration it+1
+        auto phase_a = [&](int it) {
+            const int Y = y0 + 4 * it;
+            const int sl = ring_slot(Y + 2 + w, y0) * RG::W + lane + 2;
+            R a = R(0), b = R(0);
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                cf1[k] = nf1[k];
+                cf2[k] = nf2[k];
+                a += cf1[k];
+                b += cf2[k];
+            }
+            const bool fl = nm == 0;
+            sm.c1[sl] = fl ? a : R(0);
+            sm.c2[sl] = fl ? b : R(0);
+            sm.m[sl] = nm;
+            if (w >= 2) {
+#pragma unroll
+                for (int k = 0; k < 9; ++k) {
+                    sm.stash[it & 1][w - 2][k][lane] = cf1[k];
+                    sm.stash[it & 1][w - 2][9 + k][lane] = cf2[k];
+                }
+            }
+            // issued on every path before the next row's pulls so that waiting
+            // for them leaves those in flight; rows outside the strip load out of
+            // range (no traffic)
+            yo = Y + ((w + 2) & 3);
+            nb = make_nb32(g, gxl, wrapc(yo, g.ny));
+            idx = nb.r0 + nb.x0;
+            const bool gon = yo >= y0 && yo < y0 + rows;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) gg[k] = bld<P>(src, c, 2, k, nb.up(k), gon);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if constexpr (P == P64)
+                    ho[q] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+                        hist, int(gon ? idx * 8u : kDiscard), int(q * hstride), 0));
+                else
+                    ho[q] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                        hist, int(gon ? idx * 4u : kDiscard), int(q * hstride), 0));
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            pull_f<P>(g, c, src, matr, gxl, wrapc(Y + 6 + w, g.ny), Y + 6 + w <= ylast, nf1, nf2, nm);
+            __builtin_amdgcn_sched_barrier(0);
+        };
+
+        pull_f<P>(g, c, src, matr, gxl, wrapc(y0 - 2 + w, g.ny), true, nf1, nf2, nm);
+        phase_a(-1);
+        __syncthreads();
+        phase_b(-1);
+        __syncthreads();
+        phase_a(0);
+        for (int it = 0; it < nit; ++it) {
+            __syncthreads();
+            phase_b(it);
+            __syncthreads();
+            // ---- phase C
+            {
+                Stencil<R> s;
+                const int sl[3] = {ring_slot(yo - 1, y0), ring_slot(yo, y0), ring_slot(yo + 1, y0)};
+                const int ml[3] = {mu_slot(yo - 1, y0), mu_slot(yo, y0), mu_slot(yo + 1, y0)};
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    s.c1[r] = &sm.c1[sl[r] * RG::W + lane + 2];
+                    s.c2[r] = &sm.c2[sl[r] * RG::W + lane + 2];
+                    s.m[r] = &sm.m[sl[r] * RG::W + lane + 2];
+                    s.mu1[r] = &sm.mu1[ml[r] * RG::MW + lane + 1];
+                    s.mu2[r] = &sm.mu2[ml[r] * RG::MW + lane + 1];
+                }
+                s.mu3 = sm.mu3[ml[1] * RG::MW + lane + 1];
+                const unsigned mask = out_lane ? sm.nmask[ml[1] * RG::MW + lane + 1] : kSelfBit;
+                const bool live = out_lane && yo < y0 + rows && !(mask & kSelfBit);
+                if (w >= 2) {
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) {
+                        cf1[k] = sm.stash[(it - 1) & 1][w - 2][k][lane];
+                        cf2[k] = sm.stash[(it - 1) & 1][w - 2][9 + k][lane];
+                    }
+                }
+                node_update<P, F>(g, c, s, sm.mt, nb, idx, live, mask, cf1, cf2, gg, ho, dst, hist,
+                                  hstride);
+            }
+            // phase A of the next iteration (after the last one its loads are
+            // all out of range)
+            phase_a(it + 1);
+        }
     }
 }
 
