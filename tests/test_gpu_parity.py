@@ -103,6 +103,22 @@ def test_tile_shape_invariance(tlb, rows):
     assert np.array_equal(a.read_populations(), b.read_populations())
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp16dev"])
+@pytest.mark.parametrize("rows", [8, 20, 128])
+def test_tile_shape_invariance_reduced_precision(tlb, precision, rows):
+    """The same bitwise independence of the strip height with FP32 and
+    FP16-dev storage (odd and even numbers of 4-row iterations per strip, a
+    short last strip)."""
+    p = W.random_fields(130, 70, geometry="cylinder")
+    a = tlb.from_problem(p, precision)
+    a.set_tile_rows(64)
+    a.step(50)
+    b = tlb.from_problem(p, precision)
+    b.set_tile_rows(rows)
+    b.step(50)
+    assert np.array_equal(a.read_populations(), b.read_populations())
+
+
 def test_binary_drops_small(tlb):
     p = W.binary_drops(seed=3, nx=128, ny=64, R=16)
     g, o = run_pair(tlb, p, 500)
