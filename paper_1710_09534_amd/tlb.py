@@ -466,6 +466,7 @@ class Server:
         if st != TLB_OK:
             raise TlbError(st, lib.tlb_server_last_error(None).decode())
         self.h = h
+        self._size = {}   # request id -> (nx, ny): the library writes that many nodes per field
 
     def _check(self, st):
         if st != TLB_OK:
@@ -502,6 +503,7 @@ class Server:
         r.result_fields = int(fields)
         rid = C.c_uint64()
         self._check(lib.tlb_server_submit(self.h, C.byref(r), C.byref(rid)))
+        self._size[rid.value] = (nx, ny)
         return rid.value
 
     def poll(self, rid: int) -> int:
@@ -512,9 +514,15 @@ class Server:
     def wait(self, rid: int, timeout: float = -1.0):
         self._check(lib.tlb_server_wait(self.h, rid, float(timeout)))
 
-    def result(self, rid: int, nx: int, ny: int, mask: int = F_ALL):
+    def result(self, rid: int, nx: int = None, ny: int = None, mask: int = F_ALL):
+        """Fields of a finished request; nx, ny, if given, must be its size."""
+        if rid not in self._size:
+            raise TlbError(TLB_EINVAL, "unknown request id")
+        snx, sny = self._size[rid]
+        if (nx is not None and nx != snx) or (ny is not None and ny != sny):
+            raise ValueError("request %d is %d x %d, not %s x %s" % (rid, snx, sny, nx, ny))
         names = [f for i, f in enumerate(FIELDS) if mask & (1 << i)]
-        out = np.zeros((len(names), ny, nx))
+        out = np.zeros((len(names), sny, snx))
         lat = C.c_double()
         self._check(lib.tlb_server_result(self.h, rid, mask, _dp(out), C.byref(lat)))
         return {k: out[i] for i, k in enumerate(names)}, lat.value
@@ -526,6 +534,7 @@ class Server:
 
     def release(self, rid: int):
         self._check(lib.tlb_server_release(self.h, rid))
+        self._size.pop(rid, None)
 
     def cancel(self, rid: int):
         self._check(lib.tlb_server_cancel(self.h, rid))

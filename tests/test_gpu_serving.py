@@ -91,6 +91,8 @@ def test_cancel_and_failure_isolation(tlb):
     srv.cancel(long_id)
     srv.wait(long_id, 120.0)
     assert srv.poll(long_id) == tlb.TLB_REQ_CANCELLED
+    with pytest.raises(ValueError):   # a host buffer sized for another lattice is refused
+        srv.result(ok_id, probs[0]["nx"] + 1, probs[0]["ny"])
     f, _ = srv.result(ok_id, probs[0]["nx"], probs[0]["ny"])
     p0 = dict(probs[0], steps=300)
     ref = solo(tlb, p0, "fp64")
