@@ -150,7 +150,8 @@ def leg_3d(tlb, torch, steps=100):
 def batching_leg(tlb, torch, precision="fp32", n_lattices=256, size=64, steps=200):
     """Many small lattices (the serving stream's most common size) advanced
     one at a time versus together in one batched, graph-replayed launch per
-    step."""
+    step; the same lattices one at a time with the plain FP64 path are the
+    reference."""
     from paper_1710_09534_amd import workloads as W
     rng = W.Rng(99)
     probs = [W.serving_request(W.Rng(rng.next_u64()), size, i % 3, (steps, steps))
@@ -173,11 +174,24 @@ def batching_leg(tlb, torch, precision="fp32", n_lattices=256, size=64, steps=20
     b.step(steps)
     b.sync()
     t_batch = time.perf_counter() - t0
+    del b, solvers
+    solvers = [tlb.from_problem(p, "fp64") for p in probs]
+    for s in solvers:
+        s.set_check_interval(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in solvers:
+        s.step(steps)
+    torch.cuda.synchronize()
+    t_fp64 = time.perf_counter() - t0
+    del solvers
     nodes = n_lattices * size * size
     return {"lattices": n_lattices, "size": "%dx%d" % (size, size), "precision": precision,
             "steps": steps, "one_at_a_time_mlups": round(nodes * steps / t_solo / 1e6, 1),
             "batched_mlups": round(nodes * steps / t_batch / 1e6, 1),
-            "speedup": round(t_solo / t_batch, 2)}
+            "speedup": round(t_solo / t_batch, 2),
+            "one_at_a_time_fp64_mlups": round(nodes * steps / t_fp64 / 1e6, 1),
+            "speedup_vs_fp64": round(t_fp64 / t_batch, 2)}
 
 
 def serving_leg(tlb, torch, precision="fp32", n_requests=120, steps=(1000, 4000),
