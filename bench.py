@@ -297,6 +297,30 @@ def serving_leg(tlb, torch, precision="fp32", n_requests=120, steps=(1000, 4000)
     return out
 
 
+def copy_reference(torch, mib=1024, reps=10):
+    """A plain device-to-device copy of mib MiB (torch copy_, its own kernel):
+    the practical streaming ceiling beside the 8 TB/s peak, read plus write
+    bytes per second, timed with HIP events on torch's current stream (where
+    the copies run)."""
+    nb = mib << 20
+    a = torch.ones(nb // 4, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    gbs = 2 * nb / (ms * 1e-3) / 1e9
+    del a, b
+    return {"copy_bytes_each_way": nb, "ms": round(ms, 4), "gbs_read_plus_write": round(gbs, 1),
+            "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -370,21 +394,7 @@ def main():
 
     import torch
     if args.copy_calibration:
-        nb = args.copy_calibration << 20
-        a = torch.ones(nb // 4, dtype=torch.float32, device="cuda:0")
-        b = torch.empty_like(a)
-        for _ in range(10):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ev0.record()
-        for _ in range(10):
-            b.copy_(a)
-        ev1.record()
-        torch.cuda.synchronize()
-        ms = ev0.elapsed_time(ev1) / 10
-        print(json.dumps({"copy_bytes_each_way": nb, "ms": ms,
-                          "gbs_read_plus_write": 2 * nb / (ms * 1e-3) / 1e9}), flush=True)
+        print(json.dumps(copy_reference(torch, args.copy_calibration)), flush=True)
         return
     from paper_1710_09534_amd import tlb
 
@@ -445,6 +455,7 @@ def main():
         out["bw_sweep"] = bw_sweep_leg(tlb, torch)
     if not (args.only or args.no_3d):
         out["d3q19"] = leg_3d(tlb, torch)
+    out["copy_reference"] = copy_reference(torch)
     if args.serving_full:
         # the whole seeded stream of the serving workload: 1000 requests of
         # 1000-20000 steps under a 200 GB arena (minutes of GPU time)
