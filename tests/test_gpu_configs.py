@@ -1,0 +1,196 @@
+"""The configured workloads in every storage precision against the FP64 oracle
+(GPU), element by element, and the batched call against the oracle.
+
+* compound drop between walls moving at -U/+U (512 x 256, U = 0.01; the
+  moving-wall bounce-back of Eq. 44 with its momentum term) in FP32 and
+  FP16-dev after 1000 steps: order parameters within 1e-4 of the oracle; the
+  apparent contact angles of the sheared drop after 5000 steps within 0.5 deg
+  of the FP64 run;
+* binary drops on a substrate (256 x 128, densities 10/5/1) in FP32 after 2000
+  steps: order parameters within 1e-4;
+* the 1024 x 2048 cylinder impact in FP32 for 100 steps, in the launch
+  configuration of the benchmark: order parameters within 1e-4, velocity
+  within 1e-6;
+* the reduction-consistency variant of the 64 x 64 case on the GPU in FP64:
+  with phase 2 absent, sigma_12 = 1.5e-3 and sigma_23 = 1.2e-3 leave c1 equal
+  to the run with equal tensions within 1e-12 after 1000 steps (Sec. II.B,
+  Eqs. 36-37), and both runs equal the oracle within 1e-12;
+* the members of an FP64 batch (several sizes and geometries in one launch per
+  step) equal the oracle within 1e-12.
+
+Each test prints the errors per result (c_i, u, p, mu) for the record.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1710_09534_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tlb():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1710_09534_amd import tlb as t
+    return t
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _oracle(p, steps):
+    o = oracle.Oracle(p)
+    o.init(p["c1"], p["c2"], p["ux"], p["uy"])
+    if steps:
+        o.step(steps)
+    return o
+
+
+def _errors(fg, fo):
+    return {k: float(np.abs(fg[k] - fo[k]).max()) for k in fo}
+
+
+def _fmt(e):
+    return {k: "%.2e" % v for k, v in e.items()}
+
+
+def apparent_angles(s, y_wall=0.5):
+    """Contact angles of the drop whose indicator is s (the c = 0.5 contour,
+    linear interpolation along lattice lines): the cap angle
+    2 arctan(2 H / L) from the contact length L (crossings on the first two
+    fluid rows extrapolated to the wall surface) and the apex height H over
+    all columns, and the left and right angles from a straight-line fit of
+    the contour's crossings on the first four fluid rows."""
+    ny, nx = s.shape
+
+    def ends(row):
+        xs = [x + (0.5 - row[x]) / (row[x + 1] - row[x]) for x in range(nx - 1)
+              if (row[x] - 0.5) * (row[x + 1] - 0.5) < 0]
+        return min(xs), max(xs)
+
+    rows = [1, 2, 3, 4]
+    e = np.array([ends(s[y]) for y in rows])
+    yr = np.array(rows, dtype=float)
+    aL, bL = np.polyfit(yr, e[:, 0], 1)       # x_left(y) = aL y + bL
+    aR, bR = np.polyfit(yr, e[:, 1], 1)
+    L = (aR * y_wall + bR) - (aL * y_wall + bL)
+    top = 0.0
+    for x in range(nx):
+        col = s[:, x]
+        for y in range(1, ny - 2):
+            if (col[y] - 0.5) * (col[y + 1] - 0.5) < 0:
+                top = max(top, y + (0.5 - col[y]) / (col[y + 1] - col[y]))
+    H = top - y_wall
+    cap = math.degrees(2 * math.atan(2 * H / L))
+    # angle inside the drop between the wall and the contour: at the left end
+    # the contour leans outwards (dx/dy < 0) when the angle exceeds 90 deg
+    left = 90.0 + math.degrees(math.atan(-aL))
+    right = 90.0 + math.degrees(math.atan(aR))
+    return {"cap": cap, "left": left, "right": right}
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16dev"])
+def test_compound_shear_512x256_reduced_precision(tlb, precision):
+    p = W.compound_shear(seed=0)
+    _say("case %s %s 1000 steps" % (p["name"], precision))
+    fo = _oracle(p, 1000).fields()
+    g = tlb.from_problem(p, precision)
+    g.step(1000)
+    e = _errors(g.read_fields(), fo)
+    _say("compound shear 512x256 %s errors after 1000 steps: %s" % (precision, _fmt(e)))
+    assert e["c1"] <= 1e-4 and e["c2"] <= 1e-4 and e["c3"] <= 1e-4, e
+    # the wall speed is 0.01; velocity errors stay far below it
+    assert e["ux"] <= 1e-5 and e["uy"] <= 1e-5, e
+
+
+def test_compound_shear_contact_angles_across_precisions(tlb):
+    p = W.compound_shear(seed=0)
+    ang = {}
+    for prec in ("fp64", "fp32", "fp16dev"):
+        _say("case %s %s 5000 steps" % (p["name"], prec))
+        g = tlb.from_problem(p, prec)
+        g.step(5000)
+        f = g.read_fields()
+        ang[prec] = apparent_angles(f["c1"] + f["c2"])
+    _say("compound shear apparent angles after 5000 steps: %s"
+         % {k: {a: "%.3f" % v for a, v in d.items()} for k, d in ang.items()})
+    for prec in ("fp32", "fp16dev"):
+        for a in ("cap", "left", "right"):
+            assert abs(ang[prec][a] - ang["fp64"][a]) <= 0.5, (prec, a, ang)
+    # the shear tilts the drop: the angles at its two ends differ
+    assert abs(ang["fp64"]["left"] - ang["fp64"]["right"]) > 1.0, ang
+
+
+def test_binary_drops_256x128_fp32(tlb):
+    p = W.binary_drops(seed=0)
+    _say("case %s fp32 2000 steps" % p["name"])
+    fo = _oracle(p, 2000).fields()
+    g = tlb.from_problem(p, "fp32")
+    g.step(2000)
+    e = _errors(g.read_fields(), fo)
+    _say("binary drops 256x128 fp32 errors after 2000 steps: %s" % _fmt(e))
+    assert e["c1"] <= 1e-4 and e["c2"] <= 1e-4 and e["c3"] <= 1e-4, e
+
+
+def test_cylinder_impact_1024x2048_fp32(tlb):
+    p = W.cylinder_impact(We=10, theta=90)
+    _say("case %s fp32 100 steps, 64-row strips" % p["name"])
+    fo = _oracle(p, 100).fields()
+    g = tlb.from_problem(p, "fp32")
+    g.set_tile_rows(64)
+    g.step(100)
+    e = _errors(g.read_fields(), fo)
+    _say("cylinder impact 1024x2048 fp32 errors after 100 steps: %s" % _fmt(e))
+    assert e["c1"] <= 1e-4 and e["c2"] <= 1e-4 and e["c3"] <= 1e-4, e
+    assert e["ux"] <= 1e-6 and e["uy"] <= 1e-6, e
+
+
+def test_reduction_consistency_variant_on_gpu(tlb):
+    base = W.reduction_case()
+    var = W.reduction_case(sigma=(1.5e-3, 1e-3, 1.2e-3))
+    assert var["fluid"]["sigma12"] == 1.5e-3 and var["fluid"]["sigma23"] == 1.2e-3
+    out = {}
+    for name, p in (("base", base), ("variant", var)):
+        _say("case reduction %s fp64 1000 steps" % name)
+        g = tlb.from_problem(p, "fp64")
+        g.step(1000)
+        fg = g.read_fields()
+        e = _errors(fg, _oracle(p, 1000).fields())
+        _say("reduction %s: gpu vs oracle %s" % (name, _fmt(e)))
+        assert max(e.values()) <= 1e-12, e
+        out[name] = fg
+    d = float(np.abs(out["base"]["c1"] - out["variant"]["c1"]).max())
+    _say("reduction variant: max |c1(variant) - c1(base)| = %.2e" % d)
+    assert d <= 1e-12
+    assert np.all(out["variant"]["c2"] == 0.0)
+
+
+def test_batch_members_equal_oracle(tlb):
+    probs = [W.reduction_case(), W.random_fields(100, 37, geometry="channel", U=0.01),
+             W.random_fields(130, 70, geometry="cylinder", rho=(3.0, 2.0, 1.0)),
+             W.binary_drops(seed=3, nx=128, ny=64, R=16),
+             W.random_fields(70, 50, geometry="box", gravity=(0.0, -1e-6))]
+    steps = 301
+    members = [tlb.from_problem(p, "fp64") for p in probs]
+    b = tlb.Batch(8)
+    b.set(members)
+    b.use_graph(16)
+    _say("case batch of %d fp64 lattices, %d steps" % (len(probs), steps))
+    b.step(steps)
+    b.sync()
+    for p, s in zip(probs, members):
+        o = _oracle(p, steps)
+        e = _errors(s.read_fields(), o.fields())
+        _say("batch member %s: %s" % (p["name"], _fmt(e)))
+        assert max(e.values()) <= 1e-12, (p["name"], e)
+        po = o.populations()
+        po[:, o.material != 0] = 0.0
+        assert np.abs(s.read_populations() - po).max() <= 1e-12
