@@ -36,7 +36,7 @@ def pop_bytes(precision: str) -> float:
     """Algorithmic bytes per fluid node-step: 27 populations read and
     written once, 4 history scalars read and written once."""
     if precision == "fp16dev":
-        pops = 25 * 2 + 2 * 4
+        pops = 16 * 2 + 11 * 4      # FP16 f^i_{k!=0}; FP32 rest populations and g
     else:
         pops = 27 * STORE[precision][0]
     return 2 * pops + 2 * 4 * STORE[precision][1]

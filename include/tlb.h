@@ -53,9 +53,14 @@ typedef enum {
 /* Storage precision of the populations (arithmetic in brackets):
  *  TLB_FP64    all 27 populations and the 4 history scalars in FP64 [FP64]
  *  TLB_FP32    everything in FP32 [FP32]
- *  TLB_FP16DEV the 25 moving populations f^i_{k!=0}, g_k as FP16 values
- *              scaled by a per-family power of two; the rest populations
- *              f^1_0, f^2_0 (carrying c_i) and the history in FP32 [FP32].
+ *  TLB_FP16DEV the 16 moving order-parameter populations f^i_{k!=0} as
+ *              FP16 values scaled by a per-family power of two (their
+ *              rest-state equilibria are zero, so the value is its deviation
+ *              from the rest state); the rest populations f^1_0, f^2_0
+ *              (carrying c_i), the 9 hydrodynamic populations g_k and the
+ *              history in FP32 [FP32].  (g in FP16 lets the velocity drift
+ *              under sustained shear: 5.9e-4 in c after 1000 steps between
+ *              walls at +-0.01, against 3.9e-5 with g in FP32.)
  *              Mass sums are FP64 in every mode. */
 typedef enum { TLB_FP64 = 0, TLB_FP32 = 1, TLB_FP16DEV = 2 } tlb_precision;
 
@@ -122,7 +127,7 @@ size_t tlb_workspace_bytes(int nx, int ny, tlb_precision p);
  * D > 0, M0 > 0, rho_i > 0, nu_i > 0 (else TLB_EPARAM).
  * Each family of 9 population planes and the history must stay below 2 GiB,
  * counted with rows padded to a multiple of 64 nodes: at most about 29.8 M
- * nodes in FP64 (e.g. 5400 x 5400), 59.6 M in FP32, 119.3 M in FP16-dev;
+ * nodes in FP64 (e.g. 5400 x 5400), 59.6 M in FP32 and in FP16-dev;
  * else TLB_EINVAL.
  * The library owns *out until tlb_destroy. */
 tlb_status tlb_create(int nx, int ny, tlb_precision p, const tlb_fluid* fl,
@@ -172,9 +177,12 @@ tlb_status tlb_read_fields(tlb_ctx* ctx, uint32_t field_mask, double* host_out);
  * g_0..8.  Solid nodes read 0.  Synchronizes. */
 tlb_status tlb_read_populations(tlb_ctx* ctx, double* host_out);
 
-/* Sum of c1, c2, c3 over fluid nodes in FP64 (deterministic two-pass
- * device reduction).  Returns TLB_EDIVERGED if any c is NaN/Inf.
- * Synchronizes. */
+/* Per-component mass: sums of c1, c2 and c3 = 1 - c1 - c2 over fluid nodes
+ * in FP64 (deterministic two-pass device reduction with wavefront sums),
+ * read from the history planes, i.e. of the state the last step started
+ * from; the step conserves these sums (Eqs. 2a, 3, 11a, 44), so they equal
+ * those of the current populations up to rounding.  Returns TLB_EDIVERGED
+ * if c1, c2, ux or uy is NaN/Inf at any fluid node.  Synchronizes. */
 tlb_status tlb_mass(tlb_ctx* ctx, double out[3]);
 
 /* Checkpoint: populations, history, step count.  host_buf holds
@@ -229,6 +237,24 @@ tlb_status tlb_batch_step(tlb_batch* batch, int64_t nsteps);
 tlb_status tlb_batch_sync(tlb_batch* batch);
 const char* tlb_batch_last_error(const tlb_batch* batch);
 void       tlb_batch_destroy(tlb_batch* batch);
+
+/* ---- measurement helper (not part of the method) ----
+ * Streaming references for the bandwidth the step kernel reaches: average
+ * device time of `reps` launches (after one warm-up launch) of
+ *   kind 0: a copy of `bytes` (a multiple of 16) from dev_src to dev_dst in
+ *           16-byte words (dwordx4 loads, non-temporal stores); moves
+ *           2 * bytes per launch;
+ *   kind 1: the step kernel's access shape on an nx x ny lattice without its
+ *           arithmetic: 64-column strips of tile_rows rows (a multiple of 4),
+ *           four row waves, each node reading 31 FP32 planes (27 at x - e_k of
+ *           the D2Q9 directions, wrapped, and 4 at x) and writing 31 planes at
+ *           x; dev_src and dev_dst each hold bytes >= 31 * ny * pitch * 4
+ *           (pitch = nx rounded up to 64); moves 248 bytes per node.
+ * Device buffers are the caller's; HIP events on hip_stream; synchronizes.
+ * TLB_EINVAL for bad arguments, TLB_EDEVICE for a HIP error. */
+tlb_status tlb_probe_bandwidth(int kind, int nx, int ny, int tile_rows, const void* dev_src,
+                               void* dev_dst, size_t bytes, void* hip_stream, int reps,
+                               double* ms_per_launch);
 
 /* ---- serving: continuous batching of independent solves ----
  * A server owns a worker thread that admits submitted requests (in arrival

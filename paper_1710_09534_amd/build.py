@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtlb.so")
-SOURCES = ["tlb_kernels.hip", "tlb_host.cpp", "tlb_server.cpp", "tlb3d_kernels.hip", "tlb3d_host.cpp"]
+SOURCES = ["tlb_kernels.hip", "tlb_host.cpp", "tlb_server.cpp", "tlb3d_kernels.hip", "tlb3d_host.cpp",
+           "tlb_probe.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Packed FP32 arithmetic is disabled: some of its forms have given wrong results

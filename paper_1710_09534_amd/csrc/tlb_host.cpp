@@ -41,9 +41,9 @@ Layout make_layout(int nx, int ny, int prec) {
     Layout L{};
     L.pitch = int(align_up(size_t(nx), kTileX));
     L.npad = size_t(ny) * L.pitch;
-    // FP16-dev: 8 planes of (f^1_k, f^2_k) FP16 pairs and 9 FP16 g planes, then
+    // FP16-dev: 8 planes of (f^1_k, f^2_k) FP16 pairs and 9 FP32 g planes, then
     // the two FP32 rest planes
-    size_t planes = align_up((prec == P16 ? 50 : 27 * elem_bytes(prec)) * L.npad, kAlign);
+    size_t planes = align_up((prec == P16 ? 68 : 27 * elem_bytes(prec)) * L.npad, kAlign);
     L.rest_off = planes;
     if (prec == P16) planes += align_up(2 * L.npad * 4, kAlign);
     L.pop_bytes = planes;
@@ -232,8 +232,8 @@ tlb_status upload_desc(tlb_ctx* c) {
 int ntiles(const tlb_ctx* c) { return c->grid.tiles_x * c->grid.tiles_y; }
 
 tlb_status run_mass(tlb_ctx* c) {
-    hipError_t e = launch_mass(c->prec, c->grid, consts_ptr(c),
-                               reinterpret_cast<uint8_t*>(c->ws + c->L.off_mat), popbuf(c, c->cur),
+    hipError_t e = launch_mass(c->prec, c->grid, reinterpret_cast<uint8_t*>(c->ws + c->L.off_mat),
+                               c->ws + c->L.off_hist,
                                reinterpret_cast<double*>(c->ws + c->L.off_part),
                                reinterpret_cast<double*>(c->ws + c->L.off_result), c->stream);
     if (e != hipSuccess) return dev_fail(c, e, "mass reduction");
@@ -255,7 +255,8 @@ extern "C" {
 // the step kernel addresses each family of 9 planes (and the history) as one
 // buffer with 32-bit offsets and discards stores at offset 2^31
 static bool fits_offsets(const Layout& L, int p) {
-    return 9 * L.npad * elem_bytes(p) < (size_t(1) << 31) &&
+    // FP16-dev stores g as FP32: its g family is as large as FP32's
+    return 9 * L.npad * (p == TLB_FP16DEV ? 4 : elem_bytes(p)) < (size_t(1) << 31) &&
            4 * L.npad * (p == TLB_FP64 ? 8 : 4) < (size_t(1) << 31);
 }
 
@@ -421,9 +422,10 @@ tlb_status tlb_init_fields(tlb_ctx* c, const double* c1, const double* c2, const
     std::memcpy(host.data() + n, c2, n * sizeof(double));
     if (ux) std::memcpy(host.data() + 2 * n, ux, n * sizeof(double));
     if (uy) std::memcpy(host.data() + 3 * n, uy, n * sizeof(double));
-    // FP16 storage scale per family: a power of two that maps the largest
-    // initial moving population (bounded by the velocity and mu ranges) well
-    // inside the FP16 range, with 2^6 headroom for transients.
+    // FP16 storage scale of the two order-parameter families: a power of two
+    // that maps the largest initial moving population (bounded by the
+    // velocity and mu ranges) well inside the FP16 range, with 2^6 headroom
+    // for transients.  The g family is stored as FP32 (scale 1).
     if (c->prec == P16) {
         double umax = 0.0;
         for (size_t i = 0; i < n; ++i) {
@@ -434,9 +436,8 @@ tlb_status tlb_init_fields(tlb_ctx* c, const double* c1, const double* c2, const
             umax = std::fmax(umax, std::hypot(c->mtab_host[kMatStride * m + 3],
                                               c->mtab_host[kMatStride * m + 4]));
         const double m = std::fmax(umax, 0.02);
-        const double rmax = std::fmax(c->fl.rho[0], std::fmax(c->fl.rho[1], c->fl.rho[2]));
-        const double fmaxv[3] = {m + 1e-2, m + 1e-2, rmax * m + 1e-2};
-        for (int f = 0; f < 3; ++f) {
+        const double fmaxv[2] = {m + 1e-2, m + 1e-2};
+        for (int f = 0; f < 2; ++f) {
             int ex = int(std::floor(std::log2(1024.0 / fmaxv[f])));
             c->c32.scale[f] = std::ldexp(1.0f, ex);
             c->c32.iscale[f] = std::ldexp(1.0f, -ex);

@@ -18,8 +18,9 @@ enum Precision : int { P64 = 0, P32 = 1, P16 = 2 };
 // Device views of the state.  Populations are stored SoA as 27 planes
 // q = fam*9 + k (fam 0: f^1, 1: f^2, 2: g), each plane npad elements with
 // row pitch `pitch`.  In P16 mode the rest planes q = 0 and q = 9 live in
-// the float array `rest` (two planes) and all other planes are FP16 values
-// multiplied by scale[fam].
+// the float array `rest` (two planes), the other f^1, f^2 planes are FP16
+// values multiplied by scale[fam] (paired per direction in 32-bit words) and
+// the nine g planes are FP32.
 struct PopBuf {
     void* planes;   // element type: double (P64), float (P32), _Float16 (P16)
     float* rest;    // P16 only
@@ -38,7 +39,7 @@ struct Consts {
     R lam1, lam2, lam3, lamT;    // Eqs. 7, 9
     R k12D, k34D, k4D;           // 12/D, 3D/4, 4/D
     R gx, gy;                    // gravity
-    float scale[3], iscale[3];   // P16 storage scales per family
+    float scale[3], iscale[3];   // P16 storage scales of f^1, f^2 (g: 1)
     unsigned nee;                // bit m set: material m is a velocity boundary
                                  // (non-equilibrium extrapolation, Eqs. 51-53)
     // fields used only by optional kernel parts stay last, so that adding
@@ -96,7 +97,11 @@ hipError_t launch_readout(int prec, const Grid& g, const void* consts, const uin
 hipError_t launch_populations(int prec, const Grid& g, const void* consts,
                               const uint8_t* mat, PopBuf src, int ya, int yb, double* out27,
                               hipStream_t s);
-hipError_t launch_mass(int prec, const Grid& g, const void* consts, const uint8_t* mat,
-                       PopBuf src, double* partials, double* result, hipStream_t s);
+// per-component mass and health of the history planes `hist` (double in P64,
+// float otherwise): result[0..3] = sum c1, sum c2, sum c3 over fluid nodes and
+// the count of nodes with a non-finite c1, c2, ux or uy; partials holds
+// kReduceBlocks * 4 doubles
+hipError_t launch_mass(int prec, const Grid& g, const uint8_t* mat, const void* hist,
+                       double* partials, double* result, hipStream_t s);
 
 }  // namespace tlb

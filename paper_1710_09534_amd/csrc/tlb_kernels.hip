@@ -45,12 +45,11 @@ template <> struct Tr<P32> { using R = float; using S = float; using H = float; 
 template <> struct Tr<P16> { using R = float; using S = _Float16; using H = float; };
 
 // FP16-dev population buffer: f^1_k and f^2_k (k = 1..8) share one 32-bit
-// word (f^1 in the low half) in 8 pair planes, followed by the 9 FP16 g
+// word (f^1 in the low half) in 8 pair planes, followed by the 9 FP32 g
 // planes; f^1_0 and f^2_0 live in the FP32 rest planes.  Halfword index of
-// population q = 9 f + k (f: f^1, f^2, g) at node i:
+// an order-parameter population q = 9 f + k (f: f^1, f^2; k >= 1) at node i:
 template <int P>
 __device__ __forceinline__ long half_index(int q, long npad, long i) {
-    if (q >= 18) return 16 * npad + (q - 18) * npad + i;
     const int k = q % 9;
     return 2 * ((k - 1) * npad + i) + (q / 9);
 }
@@ -60,6 +59,7 @@ __device__ __forceinline__ typename Tr<P>::R ld(const PopBuf& b, const Consts<ty
                                                 int q, long npad, long i) {
     if constexpr (P == P16) {
         if (q == 0 || q == 9) return b.rest[(q / 9) * npad + i];
+        if (q >= 18) return static_cast<const float*>(b.planes)[(8 + q - 18) * npad + i];
         return float(static_cast<const _Float16*>(b.planes)[half_index<P>(q, npad, i)]) *
                c.iscale[q / 9];
     } else {
@@ -73,6 +73,8 @@ __device__ __forceinline__ void st(const PopBuf& b, const Consts<typename Tr<P>:
     if constexpr (P == P16) {
         if (q == 0 || q == 9) {
             b.rest[(q / 9) * npad + i] = v;
+        } else if (q >= 18) {
+            static_cast<float*>(b.planes)[(8 + q - 18) * npad + i] = v;
         } else {
             static_cast<_Float16*>(b.planes)[half_index<P>(q, npad, i)] =
                 _Float16(v * c.scale[q / 9]);
@@ -433,9 +435,9 @@ template <int P>
 struct LatView {
     rsrc_t fam[3];      // f^1, f^2, g: plane k of a family at byte offset k * pstride.  P16:
                         // fam[0], fam[1] hold the (f^1_k, f^2_k) pair planes k = 1..4 and
-                        // 5..8 at offset ((k - 1) & 3) * ppstride, fam[2] the g planes
+                        // 5..8 at offset ((k - 1) & 3) * ppstride, fam[2] the FP32 g planes
     rsrc_t rest;        // P16: FP32 rest planes f^1_0 (offset 0), f^2_0 (offset rstride)
-    unsigned pstride;   // bytes per plane
+    unsigned pstride;   // bytes per plane (P16: per FP32 g plane)
     unsigned ppstride;  // P16 pair-plane bytes
     unsigned rstride;   // P16 rest-plane bytes
 };
@@ -444,7 +446,7 @@ template <int P>
 __device__ __forceinline__ LatView<P> lat_view(const PopBuf& b, long npad) {
     using S = typename Tr<P>::S;
     LatView<P> v;
-    const unsigned ps = unsigned(npad * long(sizeof(S)));
+    const unsigned ps = unsigned(npad * long(P == P16 ? 4 : sizeof(S)));
     const char* base = static_cast<const char*>(b.planes);
     if constexpr (P == P16) {
         const unsigned pp = unsigned(npad * 4);
@@ -493,21 +495,18 @@ __device__ __forceinline__ typename Tr<P>::R bld(const LatView<P>& v,
                                                           int(k * v.pstride), 0);
         return __builtin_bit_cast(float, r);
     } else {
-        // f^1_0, f^2_0 from the rest planes and g here; the f^1, f^2 pairs of
-        // k >= 1 are loaded together by bld12
-        if (k == 0 && f < 2) {
-            unsigned r = __builtin_amdgcn_raw_buffer_load_b32(v.rest, int(on ? j * 4u : kDiscard),
-                                                              int(f * v.rstride), 0);
-            return __builtin_bit_cast(float, r);
-        }
-        unsigned short r = __builtin_amdgcn_raw_buffer_load_b16(
-            v.fam[f], int(on ? j * 2u : kDiscard), int(k * v.pstride), 0);
-        return float(__builtin_bit_cast(_Float16, r)) * c.iscale[f];
+        // f^1_0, f^2_0 from the rest planes and the FP32 g planes here; the
+        // f^1, f^2 pairs of k >= 1 are loaded together by bld12
+        const unsigned r = __builtin_amdgcn_raw_buffer_load_b32(
+            f < 2 ? v.rest : v.fam[2], int(on ? j * 4u : kDiscard),
+            int(f < 2 ? f * v.rstride : k * v.pstride), 0);
+        return __builtin_bit_cast(float, r);
     }
 }
 
 // store population k of family f at byte offset `ob` within its plane
-// (`orb` for the FP32 rest planes of P16)
+// (`orb`: byte offset of a 4-byte element, for the FP32 rest and g planes of
+// P16)
 template <int P>
 __device__ __forceinline__ void bst(const LatView<P>& v, const Consts<typename Tr<P>::R>& c,
                                     int f, int k, unsigned ob, unsigned orb,
@@ -520,16 +519,13 @@ __device__ __forceinline__ void bst(const LatView<P>& v, const Consts<typename T
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), v.fam[f], int(ob),
                                               int(k * v.pstride), Policy<P>::kStore);
     } else {
-        // f^1_0, f^2_0 to the rest planes and g here; f^1, f^2 pairs of k >= 1
-        // go through bst12
-        if (k == 0 && f < 2) {
-            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), v.rest,
-                                                  int(orb), int(f * v.rstride), Policy<P>::kStore);
-            return;
-        }
-        const _Float16 h = _Float16(x * c.scale[f]);
-        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h), v.fam[f],
-                                              int(ob), int(k * v.pstride), Policy<P>::kStore);
+        // f^1_0, f^2_0 to the rest planes and g to its FP32 planes; f^1, f^2
+        // pairs of k >= 1 go through bst12
+        (void)ob;
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x),
+                                              f < 2 ? v.rest : v.fam[2], int(orb),
+                                              int(f < 2 ? f * v.rstride : k * v.pstride),
+                                              Policy<P>::kStore);
     }
 }
 
@@ -1310,62 +1306,72 @@ __global__ __launch_bounds__(kThreads) void populations_kernel(Grid g, Consts<ty
 }
 
 // ------------------------------------------------------------------- mass
-// Deterministic two-pass reduction: block b sums a fixed contiguous range
-// of nodes with a fixed tree; one block then sums the partials.
-template <int P>
-__global__ __launch_bounds__(kThreads) void mass_partial_kernel(Grid g, Consts<typename Tr<P>::R> c,
+// Per-component mass and health check (row a7 of the path).  The sums
+// sum_x c_i over the fluid nodes are conserved by the step (the equilibria
+// and sources of Eqs. 2a and 11a carry no mass, Eq. 3 fixes c3, half-way
+// bounce-back of Eq. 44 returns every population), so they are read from the
+// history planes (c1, c2, ux, uy of the state the last step started from,
+// which holds the same sums as the current populations up to rounding): 16
+// or 32 bytes per node instead of 18 pulled populations.  A node whose c1,
+// c2, ux or uy is not finite is counted (u carries the g moments).
+// Deterministic: block b owns a fixed contiguous range of the padded node
+// index space; each thread sums its nodes in order, each wavefront reduces
+// with a fixed butterfly of lane exchanges, and the four wavefronts' sums are
+// added in wave order; one block then reduces the per-block partials the same
+// way.
+
+// the four sums of a wavefront, in every lane (fixed exchange pattern)
+__device__ __forceinline__ void wave_sum4(double (&v)[4]) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] += __shfl_xor(v[q], m, 64);
+}
+
+// block-wide sums of v (kThreads threads, four wavefronts) into out[0..3]
+__device__ __forceinline__ void block_sum4(double (&v)[4], double* out) {
+    __shared__ double wsum[kThreads / 64][4];
+    wave_sum4(v);
+    const int wv = threadIdx.x / 64;
+    if ((threadIdx.x & 63) == 0)
+        for (int q = 0; q < 4; ++q) wsum[wv][q] = v[q];
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double a = 0.0;
+        for (int w = 0; w < kThreads / 64; ++w) a += wsum[w][threadIdx.x];
+        out[threadIdx.x] = a;
+    }
+}
+
+template <typename H>
+__global__ __launch_bounds__(kThreads) void mass_partial_kernel(Grid g,
                                                                 const uint8_t* __restrict__ mat,
-                                                                PopBuf src, double* __restrict__ part) {
-    __shared__ double red[4][kThreads];
-    const long n = long(g.nx) * g.ny;
+                                                                const H* __restrict__ hist,
+                                                                double* __restrict__ part) {
+    const long n = g.npad;
     const long per = (n + gridDim.x - 1) / gridDim.x;
     const long lo = long(blockIdx.x) * per;
-    const long hi_end = lo + per < n ? lo + per : n;
-    double s1 = 0.0, s2 = 0.0, s3 = 0.0, bad = 0.0;
-    for (long hi = lo + threadIdx.x; hi < hi_end; hi += kThreads) {
-        const int gy = int(hi / g.nx), gx = int(hi - long(gy) * g.nx);
-        const Nb nb = make_nb(g, gx, gy);
-        if (mat[nb.r0 + gx]) continue;
-        typename Tr<P>::R a = 0, b = 0;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) {
-            long j = nb.up(k);
-            a += ld<P>(src, c, k, g.npad, j);
-            b += ld<P>(src, c, 9 + k, g.npad, j);
-        }
-        const double da = double(a), db = double(b);
-        if (!isfinite(da) || !isfinite(db)) bad += 1.0;
-        s1 += da;
-        s2 += db;
-        s3 += 1.0 - da - db;
+    const long end = lo + per < n ? lo + per : n;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};    // sum c1, sum c2, sum c3, non-finite count
+    for (long i = lo + threadIdx.x; i < end; i += kThreads) {
+        const int x = int(i % g.pitch);
+        if (x >= g.nx || mat[i]) continue;
+        const double a = double(hist[i]), b = double(hist[n + i]);
+        const double ux = double(hist[2 * n + i]), uy = double(hist[3 * n + i]);
+        if (!isfinite(a) || !isfinite(b) || !isfinite(ux) || !isfinite(uy)) v[3] += 1.0;
+        v[0] += a;
+        v[1] += b;
+        v[2] += 1.0 - a - b;
     }
-    red[0][threadIdx.x] = s1;
-    red[1][threadIdx.x] = s2;
-    red[2][threadIdx.x] = s3;
-    red[3][threadIdx.x] = bad;
-    __syncthreads();
-    for (int w = kThreads / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w)
-            for (int q = 0; q < 4; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x < 4) part[blockIdx.x * 4 + threadIdx.x] = red[threadIdx.x][0];
+    block_sum4(v, part + 4 * blockIdx.x);
 }
 
 __global__ __launch_bounds__(kThreads) void mass_final_kernel(const double* __restrict__ part,
                                                               int nparts, double* __restrict__ out) {
-    __shared__ double red[4][kThreads];
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
     for (int i = threadIdx.x; i < nparts; i += kThreads)
-        for (int q = 0; q < 4; ++q) s[q] += part[i * 4 + q];
-    for (int q = 0; q < 4; ++q) red[q][threadIdx.x] = s[q];
-    __syncthreads();
-    for (int w = kThreads / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w)
-            for (int q = 0; q < 4; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x < 4) out[threadIdx.x] = red[threadIdx.x][0];
+        for (int q = 0; q < 4; ++q) v[q] += part[4 * i + q];
+    block_sum4(v, out);
 }
 
 template <int P>
@@ -1469,11 +1475,11 @@ hipError_t launch_populations(int prec, const Grid& g, const void* consts, const
     }
 }
 
-template <int P>
-static hipError_t mass_p(const Grid& g, const void* consts, const uint8_t* mat, PopBuf src,
-                         double* part, double* result, hipStream_t s) {
-    hipLaunchKernelGGL((mass_partial_kernel<P>), dim3(kReduceBlocks), dim3(kThreads), 0, s, g,
-                       *static_cast<const CT<P>*>(consts), mat, src, part);
+template <typename H>
+static hipError_t mass_h(const Grid& g, const uint8_t* mat, const void* hist, double* part,
+                         double* result, hipStream_t s) {
+    hipLaunchKernelGGL((mass_partial_kernel<H>), dim3(kReduceBlocks), dim3(kThreads), 0, s, g,
+                       mat, static_cast<const H*>(hist), part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(mass_final_kernel, dim3(1), dim3(kThreads), 0, s, part, kReduceBlocks,
@@ -1481,12 +1487,12 @@ static hipError_t mass_p(const Grid& g, const void* consts, const uint8_t* mat, 
     return hipGetLastError();
 }
 
-hipError_t launch_mass(int prec, const Grid& g, const void* consts, const uint8_t* mat,
-                       PopBuf src, double* partials, double* result, hipStream_t s) {
+hipError_t launch_mass(int prec, const Grid& g, const uint8_t* mat, const void* hist,
+                       double* partials, double* result, hipStream_t s) {
     switch (prec) {
-        case P64: return mass_p<P64>(g, consts, mat, src, partials, result, s);
-        case P32: return mass_p<P32>(g, consts, mat, src, partials, result, s);
-        case P16: return mass_p<P16>(g, consts, mat, src, partials, result, s);
+        case P64: return mass_h<double>(g, mat, hist, partials, result, s);
+        case P32:
+        case P16: return mass_h<float>(g, mat, hist, partials, result, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -84,6 +84,8 @@ _SIGS = {
     "tlb_checkpoint_save": (C.c_int, [_vp, _vp]),
     "tlb_checkpoint_load": (C.c_int, [_vp, _vp]),
     "tlb_time_steps": (C.c_int, [_vp, C.c_int64, _D]),
+    "tlb_probe_bandwidth": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, _vp, _vp, C.c_size_t,
+                                      _vp, C.c_int, _D]),
     "tlb_set_tile_rows": (C.c_int, [_vp, C.c_int]),
     "tlb_autotune_rows": (C.c_int, [_vp, C.c_int, C.POINTER(C.c_int)]),
     "tlb_batch_table_bytes": (C.c_size_t, [C.c_int]),
@@ -285,6 +287,21 @@ class Solver:
         best = C.c_int()
         _check(lib.tlb_autotune_rows(self.ctx, int(steps_per_candidate), C.byref(best)), self.ctx)
         return best.value
+
+
+def probe_bandwidth(kind: int, src, dst, nx: int = 0, ny: int = 0, tile_rows: int = 64,
+                    reps: int = 10, stream=None) -> float:
+    """Average ms per launch of a streaming reference (kind 0: 16-byte copy of
+    src to dst; kind 1: the step kernel's 31-plane FP32 access shape on an
+    nx x ny lattice); src, dst: torch device tensors."""
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream(src.device)
+    ms = C.c_double()
+    nbytes = min(src.numel() * src.element_size(), dst.numel() * dst.element_size())
+    _check(lib.tlb_probe_bandwidth(int(kind), int(nx), int(ny), int(tile_rows),
+                                   C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()),
+                                   nbytes, C.c_void_p(st.cuda_stream), int(reps), C.byref(ms)))
+    return ms.value
 
 
 class Batch:

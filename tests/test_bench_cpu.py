@@ -31,7 +31,7 @@ def test_algorithmic_bytes_per_node_step():
     # history in 4
     assert bench.pop_bytes("fp64") == 496
     assert bench.pop_bytes("fp32") == 248
-    assert bench.pop_bytes("fp16dev") == 148
+    assert bench.pop_bytes("fp16dev") == 184
 
 
 def test_algorithmic_bytes_per_launch_counts_fluid_nodes_and_the_material_plane():

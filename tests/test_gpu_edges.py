@@ -45,8 +45,8 @@ def _max_rows(nx, elem, hist_elem):
 
 
 @pytest.mark.parametrize("precision,nx,elem,hist", [
-    ("fp64", 5430, 8, 8), ("fp32", 7710, 4, 4), ("fp16dev", 10900, 2, 4)],
-    ids=["fp64_5430", "fp32_7710", "fp16dev_10900"])
+    ("fp64", 5430, 8, 8), ("fp32", 7710, 4, 4), ("fp16dev", 7650, 4, 4)],
+    ids=["fp64_5430", "fp32_7710", "fp16dev_7650"])
 def test_largest_lattice_sampled(tlb, precision, nx, elem, hist):
     ny = _max_rows(nx, elem, hist)
     steps = 4
