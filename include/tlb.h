@@ -185,6 +185,22 @@ tlb_status tlb_read_populations(tlb_ctx* ctx, double* host_out);
  * if c1, c2, ux or uy is NaN/Inf at any fluid node.  Synchronizes. */
 tlb_status tlb_mass(tlb_ctx* ctx, double out[3]);
 
+/* For callers that cannot allocate or wait: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid device allocation.  The sums of
+ * tlb_mass, enqueued on the context's stream without synchronizing:
+ * dev_out (device memory, 4 doubles, owned by the caller) receives sum c1,
+ * sum c2, sum c3 over fluid nodes and the count of fluid nodes whose c1, c2,
+ * ux or uy is NaN/Inf, bitwise equal to what tlb_mass computes.  The partial
+ * sums go to a static array in device memory (512 x 4 doubles, one copy per
+ * GPU, resolved in tlb_create), not to the workspace; its size does not
+ * depend on the lattice, so every lattice tlb_create accepts fits.  The call
+ * allocates nothing, launches two kernels and copies nothing to the host; it
+ * does not set the context's diverged state (the caller reads dev_out[3]).
+ * Every call on a GPU shares that GPU's array: calls that overlap on one GPU
+ * (different streams) race.  TLB_EINVAL null pointer, TLB_ESTATE before
+ * tlb_init_fields, TLB_EDEVICE launch error. */
+tlb_status tlb_mass_noalloc(tlb_ctx* ctx, double* dev_out);
+
 /* Checkpoint: populations, history, step count.  host_buf holds
  * tlb_checkpoint_bytes bytes.  A restored context continues bitwise
  * identically. */

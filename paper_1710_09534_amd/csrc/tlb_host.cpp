@@ -86,6 +86,7 @@ struct tlb_ctx {
     int n_mats = 0;
     double mtab_host[kMatStride * (kMaxMaterials + 1)] = {};
     double* health = nullptr;  // pinned host copy of the last mass result
+    double* scratch = nullptr; // this GPU's static partial sums (tlb_mass_noalloc)
     alignas(16) unsigned char desc_host[kDescBytes] = {};  // last uploaded descriptor
     bool health_pending = false;
     std::string err;
@@ -319,6 +320,10 @@ tlb_status tlb_create(int nx, int ny, tlb_precision p, const tlb_fluid* fl, void
     fill_consts(c->c64, c);
     fill_consts(c->c32, c);
     set_grid(c, default_rows(nx, ny, int(p), device_cus()));
+    if (mass_scratch(&c->scratch) != hipSuccess) {
+        delete c;
+        return fail(nullptr, TLB_EDEVICE, "static scratch of tlb_mass_noalloc not found on this device");
+    }
     if (hipHostMalloc(reinterpret_cast<void**>(&c->health), 4 * sizeof(double)) != hipSuccess) {
         delete c;
         return fail(nullptr, TLB_ENOMEM, "pinned health word");
@@ -582,6 +587,17 @@ tlb_status tlb_mass(tlb_ctx* c, double out[3]) {
         c->diverged = true;
         return fail(c, TLB_EDIVERGED, "NaN/Inf order parameter detected");
     }
+    return TLB_OK;
+}
+
+tlb_status tlb_mass_noalloc(tlb_ctx* c, double* dev_out) {
+    static_assert(kScratchDoubles >= kReduceBlocks * 4, "static scratch holds every partial sum");
+    if (!c || !dev_out) return fail(c, TLB_EINVAL, "null pointer");
+    if (!c->inited) return fail(c, TLB_ESTATE, "init_fields must precede mass");
+    if (!c->scratch) return fail(c, TLB_EDEVICE, "static scratch not resolved");
+    hipError_t e = launch_mass(c->prec, c->grid, reinterpret_cast<uint8_t*>(c->ws + c->L.off_mat),
+                               c->ws + c->L.off_hist, c->scratch, dev_out, c->stream);
+    if (e != hipSuccess) return dev_fail(c, e, "mass reduction");
     return TLB_OK;
 }
 

@@ -12,6 +12,8 @@ constexpr int kMaxMaterials = 15;
 constexpr int kTileX = 64;        // interior columns per workgroup (one wave64 row)
 constexpr int kThreads = 256;     // four wave64s per workgroup (auxiliary kernels)
 constexpr int kReduceBlocks = 512;
+constexpr int kScratchDoubles = kReduceBlocks * 4;   // static scratch of tlb_mass_noalloc
+constexpr int kMaxDevices = 64;
 
 enum Precision : int { P64 = 0, P32 = 1, P16 = 2 };
 
@@ -103,5 +105,8 @@ hipError_t launch_populations(int prec, const Grid& g, const void* consts,
 // kReduceBlocks * 4 doubles
 hipError_t launch_mass(int prec, const Grid& g, const uint8_t* mat, const void* hist,
                        double* partials, double* result, hipStream_t s);
+// device address of the current GPU's copy of the static partial-sum array
+// (kScratchDoubles doubles), resolved once per device
+hipError_t mass_scratch(double** out);
 
 }  // namespace tlb

@@ -24,7 +24,16 @@
 // The init and readout kernels use a plain 64 x 8 tile with a 2-node halo.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "tlb_internal.h"
+
+// Partial sums of the mass reduction for tlb_mass_noalloc, the entry point for
+// callers that cannot allocate: a fixed array in device memory (16 KiB), one
+// copy per GPU, kept until the process ends and shared by every such call on
+// that GPU.  In host code the array's name is only a host-side stand-in:
+// tlb::mass_scratch() gives the device address of the current GPU's copy.
+static __device__ __align__(256) double scratch[tlb::kScratchDoubles];
 
 namespace tlb {
 namespace {
@@ -1485,6 +1494,26 @@ static hipError_t mass_h(const Grid& g, const uint8_t* mat, const void* hist, do
     hipLaunchKernelGGL(mass_final_kernel, dim3(1), dim3(kThreads), 0, s, part, kReduceBlocks,
                        result);
     return hipGetLastError();
+}
+
+hipError_t mass_scratch(double** out) {
+    static std::mutex mu;
+    static double* addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        // resolved once per device, with that device current: each GPU holds
+        // its own copy of the array at its own address
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = static_cast<double*>(p);
+    }
+    *out = addr[dev];
+    return hipSuccess;
 }
 
 hipError_t launch_mass(int prec, const Grid& g, const uint8_t* mat, const void* hist,

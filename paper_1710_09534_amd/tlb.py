@@ -80,6 +80,7 @@ _SIGS = {
     "tlb_read_fields": (C.c_int, [_vp, C.c_uint32, _D]),
     "tlb_read_populations": (C.c_int, [_vp, _D]),
     "tlb_mass": (C.c_int, [_vp, _D]),
+    "tlb_mass_noalloc": (C.c_int, [_vp, _vp]),
     "tlb_checkpoint_bytes": (C.c_int, [_vp, C.POINTER(C.c_size_t)]),
     "tlb_checkpoint_save": (C.c_int, [_vp, _vp]),
     "tlb_checkpoint_load": (C.c_int, [_vp, _vp]),
@@ -261,6 +262,14 @@ class Solver:
         out = np.zeros(3)
         _check(lib.tlb_mass(self.ctx, _dp(out)), self.ctx)
         return out
+
+    def mass_noalloc(self, dev_out):
+        """Enqueue the mass sums into dev_out (a float64 device tensor of 4
+        elements: sum c1, c2, c3, non-finite count) without synchronizing."""
+        import torch
+        if dev_out.dtype != torch.float64 or dev_out.numel() < 4 or not dev_out.is_cuda:
+            raise ValueError("dev_out must be a float64 device tensor of at least 4 elements")
+        _check(lib.tlb_mass_noalloc(self.ctx, C.c_void_p(dev_out.data_ptr())), self.ctx)
 
     def checkpoint_save(self) -> bytes:
         n = C.c_size_t()
