@@ -321,6 +321,81 @@ def copy_reference(torch, mib=1024, reps=10):
             "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}
 
 
+def stream_reference(tlb, torch, mib=1024, nx=1024, ny=2048, rows=64, reps=20):
+    """Hand-written streaming references (the library's probe kernels), read
+    plus write bytes per second: a copy in 16-byte words (dwordx4) of mib MiB,
+    and the step kernel's FP32 access shape without its arithmetic (31 planes
+    read at the pulled offsets and written, 248 B per node) on the benchmark
+    lattice with the benchmark's 64-row strips."""
+    nb = mib << 20
+    a = torch.ones(nb // 4, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    ms0 = tlb.probe_bandwidth(0, a, b, reps=reps)
+    del a, b
+    pitch = -(-nx // 64) * 64
+    n31 = 31 * pitch * ny
+    a = torch.ones(n31, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    ms1 = tlb.probe_bandwidth(1, a, b, nx=nx, ny=ny, tile_rows=rows, reps=reps)
+    del a, b
+    g0 = 2 * nb / (ms0 * 1e-3) / 1e9
+    g1 = 248.0 * nx * ny / (ms1 * 1e-3) / 1e9
+    return {"copy16": {"bytes_each_way": nb, "ms": round(ms0, 4), "gbs_read_plus_write": round(g0, 1),
+                       "frac_of_peak": round(g0 / HBM_PEAK_GBS, 4)},
+            "step_shape_fp32": {"lattice": "%dx%d" % (nx, ny), "tile_rows": rows,
+                                "ms": round(ms1, 4), "gbs_read_plus_write": round(g1, 1),
+                                "frac_of_peak": round(g1 / HBM_PEAK_GBS, 4)}}
+
+
+def config_table(tlb, torch, cpu=True, gpu_steps=400, oracle_budget_s=2.0):
+    """Per-configuration rates: the 64x64 reduction case, binary drops
+    256x128, the compound drop between moving walls 512x256 and the
+    1024x2048 cylinder impact, each on the GPU in every storage precision
+    (step-kernel device time from HIP events over gpu_steps launches) and,
+    with cpu, the FP64 oracle on one thread and on all host cores (as many
+    steps as fit oracle_budget_s after one untimed step; the rate is
+    extrapolated from that sample).  The three small lattices fit in the
+    memory-side cache, so only the cylinder row's %HBM is a roofline figure."""
+    from paper_1710_09534_amd import workloads as W
+    rows = [("C1 reduction 64x64", W.reduction_case()),
+            ("C2 binary drops 256x128", W.binary_drops(seed=0)),
+            ("C3 compound drop under shear 512x256", W.compound_shear(seed=0)),
+            ("C4 cylinder impact 1024x2048", W.cylinder_impact(We=10.0, theta=90.0))]
+    out = []
+    cores = None
+    if cpu:
+        import oracle
+        cores = oracle.Oracle.num_threads()
+    for name, prob in rows:
+        n = prob["nx"] * prob["ny"]
+        row = {"config": name, "nodes": n}
+        for prec in ("fp64", "fp32", "fp16dev"):
+            s = tlb.from_problem(prob, prec)
+            s.set_check_interval(0)
+            s.time_steps(20)
+            kms = s.time_steps(gpu_steps)
+            del s
+            torch.cuda.synchronize()
+            row["gpu_%s_mlups" % prec] = round(n / kms / 1e3, 1)
+            if name.startswith("C4"):
+                gbs = algorithmic_bytes(prob, prec) / (kms * 1e-3) / 1e9
+                row["hbm_frac_%s" % prec] = round(gbs / HBM_PEAK_GBS, 4)
+        if cpu:
+            import oracle
+            r_all, k_all = oracle_rate(prob, oracle_budget_s, 2000)
+            oracle.Oracle.set_num_threads(1)
+            try:
+                r_one, k_one = oracle_rate(prob, oracle_budget_s, 2000)
+            finally:
+                oracle.Oracle.set_num_threads(cores)
+            row["oracle_1thread_mlups"] = round(r_one, 3)
+            row["oracle_all_cores_mlups"] = round(r_all, 3)
+            row["oracle_steps_timed"] = [k_one, k_all]
+        out.append(row)
+        print("# config %s: %s" % (name, row), file=sys.stderr, flush=True)
+    return {"oracle_cores": cores, "cpu_model": cpu_model() if cpu else None, "rows": out}
+
+
 def cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -456,6 +531,9 @@ def main():
     if not (args.only or args.no_3d):
         out["d3q19"] = leg_3d(tlb, torch)
     out["copy_reference"] = copy_reference(torch)
+    out["stream_reference"] = stream_reference(tlb, torch)
+    if not args.only:
+        out["configs"] = config_table(tlb, torch, cpu=not args.no_cpu)
     if args.serving_full:
         # the whole seeded stream of the serving workload: 1000 requests of
         # 1000-20000 steps under a 200 GB arena (minutes of GPU time)

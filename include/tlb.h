@@ -62,7 +62,16 @@ typedef enum {
  *              under sustained shear: 5.9e-4 in c after 1000 steps between
  *              walls at +-0.01, against 3.9e-5 with g in FP32.)
  *              Mass sums are FP64 in every mode. */
-typedef enum { TLB_FP64 = 0, TLB_FP32 = 1, TLB_FP16DEV = 2 } tlb_precision;
+/* The two sentinels give the enum the range of a 32-bit int, so that any int
+ * a caller passes is a valid value of the type (the library then refuses the
+ * unknown ones with TLB_EINVAL); they are not precisions. */
+typedef enum {
+    TLB_FP64 = 0,
+    TLB_FP32 = 1,
+    TLB_FP16DEV = 2,
+    TLB_PRECISION_RANGE_MIN_ = -0x7fffffff - 1,
+    TLB_PRECISION_RANGE_MAX_ = 0x7fffffff
+} tlb_precision;
 
 /* Fluid properties (Sec. II.A). */
 typedef struct {
@@ -278,9 +287,12 @@ tlb_status tlb_probe_bandwidth(int kind, int nx, int ny, int tile_rows, const vo
  * and a block of the caller's device arena are free, keeps their populations
  * resident, and advances all running requests together with the batched step
  * kernel, quantum_steps at a time (a quantum also ends at the next
- * completion).  Finished requests are checked for NaN/Inf (a diverged request
- * fails alone), read out to host memory and release their memory for waiting
- * requests.  A request's result is bitwise the same alone or in any mix.
+ * completion).  Set-up and readout of requests run on a second stream of the
+ * server while the others' quantum is in flight.  Running requests are
+ * checked for NaN/Inf every tlb_server_set_check_steps steps and once more
+ * when they finish (a diverged request fails alone), then read out to host
+ * memory and release their memory for waiting requests.  A request's result
+ * is bitwise the same alone or in any mix.
  * Time to solution = completion - submission (host steady clock). */
 enum { TLB_REQ_QUEUED = 0, TLB_REQ_RUNNING = 1, TLB_REQ_DONE = 2, TLB_REQ_FAILED = 3,
        TLB_REQ_CANCELLED = 4 };
@@ -311,6 +323,11 @@ typedef struct tlb_server tlb_server;
 tlb_status tlb_server_create(void* dev_arena, size_t arena_bytes, int max_slots,
                              tlb_precision p, int64_t quantum_steps, void* hip_stream,
                              tlb_server** out);
+/* Interval of the mass/NaN health check of running requests (default 1000
+ * steps): every `steps` steps each running request's check is queued behind
+ * its quantum, and a request whose c1, c2, ux or uy is no longer finite fails
+ * with TLB_EDIVERGED at that quantum boundary (the others run on). */
+tlb_status tlb_server_set_check_steps(tlb_server* s, int64_t steps);
 /* TLB_ENOMEM if the request can never fit the arena */
 tlb_status tlb_server_submit(tlb_server* s, const tlb_request* req, uint64_t* id);
 tlb_status tlb_server_poll(tlb_server* s, uint64_t id, int* state);

@@ -232,14 +232,16 @@ tlb_status upload_desc(tlb_ctx* c) {
 
 int ntiles(const tlb_ctx* c) { return c->grid.tiles_x * c->grid.tiles_y; }
 
-tlb_status run_mass(tlb_ctx* c) {
+tlb_status run_mass(tlb_ctx* c, hipStream_t s) {
     hipError_t e = launch_mass(c->prec, c->grid, reinterpret_cast<uint8_t*>(c->ws + c->L.off_mat),
                                c->ws + c->L.off_hist,
                                reinterpret_cast<double*>(c->ws + c->L.off_part),
-                               reinterpret_cast<double*>(c->ws + c->L.off_result), c->stream);
+                               reinterpret_cast<double*>(c->ws + c->L.off_result), s);
     if (e != hipSuccess) return dev_fail(c, e, "mass reduction");
     return TLB_OK;
 }
+
+tlb_status run_mass(tlb_ctx* c) { return run_mass(c, c->stream); }
 
 // reads the pinned copy of the last health check if it has landed
 void poll_health(tlb_ctx* c) {
@@ -324,11 +326,8 @@ tlb_status tlb_create(int nx, int ny, tlb_precision p, const tlb_fluid* fl, void
         delete c;
         return fail(nullptr, TLB_EDEVICE, "static scratch of tlb_mass_noalloc not found on this device");
     }
-    if (hipHostMalloc(reinterpret_cast<void**>(&c->health), 4 * sizeof(double)) != hipSuccess) {
-        delete c;
-        return fail(nullptr, TLB_ENOMEM, "pinned health word");
-    }
-    std::memset(c->health, 0, 4 * sizeof(double));
+    // the pinned health word of the periodic check is allocated by the first
+    // check (contexts whose checks are off, such as the server's, never hold one)
     *out = c;
     return TLB_OK;
 }
@@ -481,6 +480,12 @@ static tlb_status step_impl(tlb_ctx* c, int64_t nsteps, bool checks) {
         ++c->steps;
         if (checks && c->check_interval > 0 && ++c->since_check >= c->check_interval) {
             c->since_check = 0;
+            if (!c->health) {
+                if (hipHostMalloc(reinterpret_cast<void**>(&c->health), 4 * sizeof(double)) !=
+                    hipSuccess)
+                    return fail(c, TLB_ENOMEM, "pinned health word");
+                std::memset(c->health, 0, 4 * sizeof(double));
+            }
             tlb_status st = run_mass(c);
             if (st != TLB_OK) return st;
             e = hipMemcpyAsync(c->health, c->ws + c->L.off_result, 4 * sizeof(double),
@@ -589,6 +594,20 @@ tlb_status tlb_mass(tlb_ctx* c, double out[3]) {
     }
     return TLB_OK;
 }
+
+extern "C++" {
+namespace tlb {
+int health_enqueue(tlb_ctx* c, hipStream_t s, double* host4) {
+    if (!c || !host4 || !c->inited) return TLB_EINVAL;
+    tlb_status st = run_mass(c, s);
+    if (st != TLB_OK) return st;
+    hipError_t e = hipMemcpyAsync(host4, c->ws + c->L.off_result, 4 * sizeof(double),
+                                  hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return dev_fail(c, e, "health copy");
+    return TLB_OK;
+}
+}  // namespace tlb
+}  // extern "C++"
 
 tlb_status tlb_mass_noalloc(tlb_ctx* c, double* dev_out) {
     static_assert(kScratchDoubles >= kReduceBlocks * 4, "static scratch holds every partial sum");

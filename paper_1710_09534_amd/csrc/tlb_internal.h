@@ -110,3 +110,13 @@ hipError_t launch_mass(int prec, const Grid& g, const uint8_t* mat, const void* 
 hipError_t mass_scratch(double** out);
 
 }  // namespace tlb
+
+struct tlb_ctx;
+namespace tlb {
+// queues the mass/health reduction of a context on stream s (which must be
+// ordered after the context's last step) and the copy of its four results
+// (sum c1, c2, c3, non-finite count) to pinned host memory host4; the
+// serving loop uses it to check running requests behind their quantum
+int health_enqueue(tlb_ctx* c, hipStream_t s, double* host4);
+
+}  // namespace tlb

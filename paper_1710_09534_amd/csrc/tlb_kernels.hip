@@ -538,7 +538,12 @@ __device__ __forceinline__ void bst(const LatView<P>& v, const Consts<typename T
     }
 }
 
-// f^1_k and f^2_k at node j together: one load of the pair word in P16
+// f^1_k and f^2_k at node j together: one load of the pair word in P16.
+// P16 keeps the moving populations (k >= 1) in registers in their stored,
+// scaled form S_i f^i_k (S_i = c.scale[i], a power of two, so the scaling is
+// exact): the step kernel folds S_i into its per-node collision terms and
+// 1/S_i into the moment sums (sum_pop) instead of converting every
+// population on load and on store.
 template <int P>
 __device__ __forceinline__ void bld12(const LatView<P>& v, const Consts<typename Tr<P>::R>& c,
                                       int k, unsigned j, bool on, typename Tr<P>::R& x1,
@@ -548,8 +553,8 @@ __device__ __forceinline__ void bld12(const LatView<P>& v, const Consts<typename
             const unsigned r = __builtin_amdgcn_raw_buffer_load_b32(
                 v.fam[(k - 1) >> 2], int(on ? j * 4u : kDiscard),
                 int(unsigned((k - 1) & 3) * v.ppstride), 0);
-            x1 = float(__builtin_bit_cast(_Float16, (unsigned short)(r & 0xffffu))) * c.iscale[0];
-            x2 = float(__builtin_bit_cast(_Float16, (unsigned short)(r >> 16))) * c.iscale[1];
+            x1 = float(__builtin_bit_cast(_Float16, (unsigned short)(r & 0xffffu)));
+            x2 = float(__builtin_bit_cast(_Float16, (unsigned short)(r >> 16)));
             return;
         }
     }
@@ -558,14 +563,15 @@ __device__ __forceinline__ void bld12(const LatView<P>& v, const Consts<typename
 }
 
 // store f^1_k and f^2_k of one node (byte offsets ob of an S element, o4 of a
-// 4-byte element): one store of the pair word in P16
+// 4-byte element): one store of the pair word in P16, whose moving
+// populations arrive already scaled (see bld12)
 template <int P>
 __device__ __forceinline__ void bst12(const LatView<P>& v, const Consts<typename Tr<P>::R>& c,
                                       int k, unsigned ob, unsigned o4, typename Tr<P>::R x1,
                                       typename Tr<P>::R x2) {
     if constexpr (P == P16) {
         if (k > 0) {
-            const _Float16 h1 = _Float16(x1 * c.scale[0]), h2 = _Float16(x2 * c.scale[1]);
+            const _Float16 h1 = _Float16(x1), h2 = _Float16(x2);
             const unsigned w = unsigned(__builtin_bit_cast(unsigned short, h1)) |
                                (unsigned(__builtin_bit_cast(unsigned short, h2)) << 16);
             __builtin_amdgcn_raw_buffer_store_b32(w, v.fam[(k - 1) >> 2], int(o4),
@@ -576,6 +582,23 @@ __device__ __forceinline__ void bst12(const LatView<P>& v, const Consts<typename
     }
     bst<P>(v, c, 0, k, ob, o4, x1);
     bst<P>(v, c, 1, k, ob, o4, x2);
+}
+
+// c_i = sum_k f^i_k (Eq. 13a) of the nine pulled populations of family i,
+// in the order k = 0..8; in P16 the moving ones enter as S_i f^i_k times the
+// exact factor 1/S_i
+template <int P>
+__device__ __forceinline__ typename Tr<P>::R sum_pop(const Consts<typename Tr<P>::R>& c, int i,
+                                                     const typename Tr<P>::R* v) {
+    typename Tr<P>::R a = v[0];
+#pragma unroll
+    for (int k = 1; k < 9; ++k) {
+        if constexpr (P == P16)
+            a = __builtin_fmaf(v[k], c.iscale[i], a);
+        else
+            a += v[k];
+    }
+    return a;
 }
 
 template <int P>
@@ -748,11 +771,19 @@ __device__ __forceinline__ void node_update(const Grid& g, const Consts<typename
     const R em1 = c.eta1 * o.mu1, em2 = c.eta2 * o.mu2;
     const R fsg = R(1) - R(0.5) * o.itg;
     const R om1 = R(1) - c.itau1, om2 = R(1) - c.itau2, omg = R(1) - o.itg;
-    const R P1 = c.itau1 * em1, P2 = c.itau2 * em2;
-    const R V1x = R(3) * (c.itau1 * o.c1 * o.ux + c.fs1 * d1x);
-    const R V1y = R(3) * (c.itau1 * o.c1 * o.uy + c.fs1 * d1y);
-    const R V2x = R(3) * (c.itau2 * o.c2 * o.ux + c.fs2 * d2x);
-    const R V2y = R(3) * (c.itau2 * o.c2 * o.uy + c.fs2 * d2y);
+    // P16: f1, f2 (k >= 1) hold S_i f^i_k, so every term added to them is
+    // scaled by S_i too (exactly: S_i is a power of two)
+    R S1 = R(1), S2 = R(1);
+    if constexpr (P == P16) {
+        S1 = c.scale[0];
+        S2 = c.scale[1];
+    }
+    const R P1 = S1 * (c.itau1 * em1), P2 = S2 * (c.itau2 * em2);
+    const R V1x = S1 * (R(3) * (c.itau1 * o.c1 * o.ux + c.fs1 * d1x));
+    const R V1y = S1 * (R(3) * (c.itau1 * o.c1 * o.uy + c.fs1 * d1y));
+    const R V2x = S2 * (R(3) * (c.itau2 * o.c2 * o.ux + c.fs2 * d2x));
+    const R V2y = S2 * (R(3) * (c.itau2 * o.c2 * o.uy + c.fs2 * d2y));
+    const R sc1 = S1 * o.c1, sc2 = S2 * o.c2;
     const R Ax = o.grx + R(3) * o.fx, Ay = o.gry + R(3) * o.fy;
     const R uA = o.ux * Ax + o.uy * Ay;
     const R G1x = R(3) * (fsg * o.fx + o.fax), G1y = R(3) * (fsg * o.fy + o.fay);
@@ -778,8 +809,8 @@ __device__ __forceinline__ void node_update(const Grid& g, const Consts<typename
             const unsigned sb = sn * unsigned(sizeof(typename Tr<P>::S)), s4 = sn * 4u;
             // e_k.V_i at u_w is 3 e_k.u_w a_i with a_i = c_i / tau_i + (1 - 1/(2 tau_i))
             // (c_i - c_i^old); e_k.G1 = 3 fsg e_k.F + 3 am e_k.u_w, G0 = 3 fsg u_w.F
-            const R a1 = c.itau1 * o.c1 + c.fs1 * (o.c1 - ho[0]);
-            const R a2 = c.itau2 * o.c2 + c.fs2 * (o.c2 - ho[1]);
+            const R a1 = S1 * (c.itau1 * o.c1 + c.fs1 * (o.c1 - ho[0]));
+            const R a2 = S2 * (c.itau2 * o.c2 + c.fs2 * (o.c2 - ho[1]));
             const R wF = uwx * o.fx + uwy * o.fy;
             const R wA = uwx * Ax + uwy * Ay;
             const R ww = uwx * uwx + uwy * uwy;
@@ -793,8 +824,8 @@ __device__ __forceinline__ void node_update(const Grid& g, const Consts<typename
                 const R skw = w * (ew * (R(3) + R(4.5) * ew) - R(1.5) * ww);
                 const R eA = R(EX[k]) * Ax + R(EY[k]) * Ay;
                 const R eF = R(EX[k]) * o.fx + R(EY[k]) * o.fy;
-                const R f1u = om1 * (f1[k] + R(3) * w * o.c1 * (ew - eu)) + w * (P1 + R(3) * ew * a1);
-                const R f2u = om2 * (f2[k] + R(3) * w * o.c2 * (ew - eu)) + w * (P2 + R(3) * ew * a2);
+                const R f1u = om1 * (f1[k] + R(3) * w * sc1 * (ew - eu)) + w * (P1 + R(3) * ew * a1);
+                const R f2u = om2 * (f2[k] + R(3) * w * sc2 * (ew - eu)) + w * (P2 + R(3) * ew * a2);
                 const R gu = omg * (gg[k] + o.rho * (skw - sku)) +
                              w * (Pg + R(3) * (fsg * (eF - wF) + o.am * ew)) +
                              skw * (Rg + fsg * (eA - wA));
@@ -834,7 +865,7 @@ __device__ __forceinline__ void node_update(const Grid& g, const Consts<typename
                 const R corr = -R(6) * wgt<R>(k) * (R(EX[k]) * tm[3] + R(EY[k]) * tm[4]);
                 const unsigned sn = nb.dn(k);
                 const unsigned sb = sn * unsigned(sizeof(typename Tr<P>::S)), s4 = sn * 4u;
-                bst12<P>(dst, c, OPP[k], sb, s4, f1[k] + corr * o.c1, f2[k] + corr * o.c2);
+                bst12<P>(dst, c, OPP[k], sb, s4, f1[k] + corr * sc1, f2[k] + corr * sc2);
                 bst<P>(dst, c, 2, OPP[k], sb, s4, g2[k] + corr * o.rho);
             }
         }
@@ -892,12 +923,7 @@ __device__ __forceinline__ void step_tile(const Grid& g, const Consts<typename T
         const bool act = lane < 16;
         auto halo_a = [&](int it) {
             const int Y = y0 + 4 * it;
-            R a = R(0), b = R(0);
-#pragma unroll
-            for (int k = 0; k < 9; ++k) {
-                a += nf1[k];
-                b += nf2[k];
-            }
+            const R a = sum_pop<P>(c, 0, nf1), b = sum_pop<P>(c, 1, nf2);
             if (act) {
                 const int sl = ring_slot(Y + 2 + hr, y0) * RG::W + ccol;
                 const bool fl = nm == 0;
@@ -1055,14 +1081,12 @@ __device__ __forceinline__ void step_tile(const Grid& g, const Consts<typename T
         auto phase_a = [&](int it) {
             const int Y = y0 + 4 * it;
             const int sl = ring_slot(Y + 2 + w, y0) * RG::W + lane + 2;
-            R a = R(0), b = R(0);
 #pragma unroll
             for (int k = 0; k < 9; ++k) {
                 cf1[k] = nf1[k];
                 cf2[k] = nf2[k];
-                a += cf1[k];
-                b += cf2[k];
             }
+            const R a = sum_pop<P>(c, 0, cf1), b = sum_pop<P>(c, 1, cf2);
             const bool fl = nm == 0;
             sm.c1[sl] = fl ? a : R(0);
             sm.c2[sl] = fl ? b : R(0);

@@ -7,11 +7,16 @@
 // device arena are free (a request that does not fit yet does not block the
 // ones behind it), initialises them, and advances every running lattice in
 // shared launches of the batched step kernel, a quantum of steps at a time
-// (the quantum ends at the next completion).  At a quantum boundary finished
-// requests are checked (mass / NaN), read out to host memory and released,
-// which frees room for waiting requests.  A request's result does not depend
-// on what else runs (the batched kernel computes every lattice exactly as a
-// lone one).
+// (the quantum ends at the next completion).  Two streams: the quanta run on
+// the caller's stream; set-up (create, geometry, initial fields) and readout
+// (mass, fields) of requests run on the server's own I/O stream while a
+// quantum is in flight, so they overlap the stepping of the others.  Every
+// check_steps steps a running request's mass/NaN health check is queued
+// behind its quantum; a diverged request fails at that boundary instead of
+// burning its whole step budget.  Finished requests are read out to host
+// memory and released, which frees room for waiting requests.  A request's
+// result does not depend on what else runs (the batched kernel computes every
+// lattice exactly as a lone one).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -98,6 +103,7 @@ struct Request {
     Clock::time_point arrival, done;
     size_t ws_off = 0, ws_bytes = 0;
     tlb_ctx* ctx = nullptr;
+    int64_t since_check = 0;      // steps since the last health check
     std::vector<double> result;   // popcount(keep) * ny*nx
 };
 
@@ -110,7 +116,10 @@ struct tlb_server {
     int max_slots;
     int prec;
     int64_t quantum;
-    hipStream_t stream;
+    int64_t check_steps = 1000;   // health check interval of running requests
+    hipStream_t stream;           // quanta (caller's)
+    hipStream_t io = nullptr;     // set-up and readout (the server's)
+    double* health = nullptr;     // pinned: 4 doubles per slot
     Arena alloc;
     size_t table_off = 0;
     tlb_batch* batch = nullptr;
@@ -147,10 +156,11 @@ int popcount10(uint32_t m) {
     return n;
 }
 
-// set up a request's context inside its arena block (worker thread)
+// set up a request's context inside its arena block (worker thread, on the
+// I/O stream; returns when the initial state is on the device)
 bool start_request(tlb_server* s, Request& r) {
     tlb_status st = tlb_create(r.nx, r.ny, tlb_precision(s->prec), &r.fluid, s->arena + r.ws_off,
-                               r.ws_bytes, s->stream, &r.ctx);
+                               r.ws_bytes, s->io, &r.ctx);
     if (st == TLB_OK)
         st = tlb_set_geometry(r.ctx, r.px, r.py, r.material.data(), r.mats.data(),
                               int(r.mats.size()), nullptr);
@@ -175,7 +185,8 @@ bool start_request(tlb_server* s, Request& r) {
     return true;
 }
 
-// read out a finished request (worker thread); false on divergence / error
+// read out a finished request (worker thread, on the I/O stream, after the
+// quantum that finished it has completed); false on divergence / error
 bool finish_request(tlb_server* s, Request& r) {
     (void)s;
     double m[3];
@@ -209,15 +220,37 @@ void release_request(tlb_server* s, Request& r) {
     }
 }
 
+void fail_request(tlb_server* s, Request& r, tlb_status st, const std::string& why) {
+    // caller holds s->mu
+    release_request(s, r);
+    r.state = TLB_REQ_FAILED;
+    if (r.status == TLB_OK) r.status = st;
+    if (r.error.empty()) r.error = why;
+    r.done = Clock::now();
+    ++s->failed;
+    s->cv_done.notify_all();
+}
+
+// One iteration: (1) the quantum of the running requests is queued on the
+// compute stream, with the health checks that fall due behind it; (2) while
+// it runs, requests that finished at the previous boundary are read out and
+// released, and queued requests that fit are set up, both on the I/O stream;
+// (3) after the quantum, due health checks are read (a request with a
+// non-finite c1, c2, ux or uy fails now), finished requests move to the
+// readout list, and new requests join the batch.
 void worker_loop(tlb_server* s) {
     // every request fails if this thread cannot use the server's device
     const bool dev_ok = hipSetDevice(s->device) == hipSuccess;
     bool composition_changed = true;
+    std::vector<std::shared_ptr<Request>> to_finish, ready;
     for (;;) {
-        std::vector<std::shared_ptr<Request>> admitted;
+        std::vector<std::shared_ptr<Request>> run;
         {
             std::unique_lock<std::mutex> lk(s->mu);
-            s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty() || !s->running.empty(); });
+            s->cv_work.wait(lk, [&] {
+                return s->stop || !s->queue.empty() || !s->running.empty() || !to_finish.empty() ||
+                       !ready.empty();
+            });
             if (s->stop) break;
             // drop cancelled requests
             for (auto it = s->queue.begin(); it != s->queue.end();) {
@@ -230,9 +263,80 @@ void worker_loop(tlb_server* s) {
                     ++it;
                 }
             }
-            // admit in arrival order whatever fits now
+            // new requests join at this boundary; cancelled running ones leave
+            for (auto& r : ready) s->running.push_back(r);
+            if (!ready.empty()) composition_changed = true;
+            ready.clear();
+            for (auto it = s->running.begin(); it != s->running.end();) {
+                if ((*it)->cancel) {
+                    release_request(s, **it);
+                    (*it)->state = TLB_REQ_CANCELLED;
+                    (*it)->done = Clock::now();
+                    it = s->running.erase(it);
+                    composition_changed = true;
+                    s->cv_done.notify_all();
+                } else {
+                    ++it;
+                }
+            }
+            run = s->running;
+        }
+        if (!run.empty() && composition_changed) {
+            std::vector<tlb_ctx*> ctxs;
+            for (auto& r : run) ctxs.push_back(r->ctx);
+            const tlb_status bst = tlb_batch_set(s->batch, ctxs.data(), int(ctxs.size()));
+            if (bst != TLB_OK) {
+                std::lock_guard<std::mutex> lk(s->mu);
+                const std::string why = tlb_batch_last_error(s->batch);
+                for (auto& r : run) fail_request(s, *r, bst, why);
+                s->running.clear();
+                continue;
+            }
+            composition_changed = false;
+        }
+        // (1) queue the quantum and the due health checks
+        int64_t q = s->quantum;
+        double nodes = 0.0;
+        for (auto& r : run) {
+            q = std::min(q, r->remaining);
+            nodes += double(r->nx) * r->ny;
+        }
+        const auto t0 = Clock::now();
+        tlb_status st = TLB_OK;
+        std::vector<int> checked;
+        if (!run.empty()) {
+            st = tlb_batch_step(s->batch, q);
+            for (size_t i = 0; st == TLB_OK && i < run.size(); ++i) {
+                Request& r = *run[i];
+                if (r.remaining - q > 0 && r.since_check + q >= s->check_steps) {
+                    st = tlb_status(tlb::health_enqueue(r.ctx, s->stream, s->health + 4 * i));
+                    checked.push_back(int(i));
+                }
+            }
+        }
+        // (2) while the quantum runs: readout of the previous boundary's
+        // finished requests, set-up of queued requests that fit
+        for (auto& rp : to_finish) {
+            const bool ok = rp->status == TLB_OK && finish_request(s, *rp);
+            std::lock_guard<std::mutex> lk(s->mu);
+            release_request(s, *rp);
+            rp->done = Clock::now();
+            if (ok) {
+                rp->state = TLB_REQ_DONE;
+                ++s->completed;
+            } else {
+                rp->state = TLB_REQ_FAILED;
+                if (rp->status == TLB_OK) rp->status = TLB_EDEVICE;
+                ++s->failed;
+            }
+            s->cv_done.notify_all();
+        }
+        to_finish.clear();
+        std::vector<std::shared_ptr<Request>> admitted;
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
             for (auto it = s->queue.begin(); it != s->queue.end();) {
-                if (int(s->running.size() + admitted.size()) >= s->max_slots) break;
+                if (int(run.size() + admitted.size()) >= s->max_slots) break;
                 Request& r = **it;
                 size_t off;
                 if (s->alloc.alloc(r.ws_bytes, &off)) {
@@ -251,102 +355,55 @@ void worker_loop(tlb_server* s) {
                 rp->status = TLB_EDEVICE;
             }
             if (dev_ok && start_request(s, *rp)) {
-                std::lock_guard<std::mutex> lk(s->mu);
-                s->running.push_back(rp);
-                composition_changed = true;
+                ready.push_back(rp);
             } else {
                 std::lock_guard<std::mutex> lk(s->mu);
-                release_request(s, *rp);
-                rp->state = TLB_REQ_FAILED;
-                rp->done = Clock::now();
-                ++s->failed;
-                s->cv_done.notify_all();
+                fail_request(s, *rp, rp->status != TLB_OK ? rp->status : TLB_EDEVICE, rp->error);
             }
-        }
-        std::vector<std::shared_ptr<Request>> run;
-        {
-            std::lock_guard<std::mutex> lk(s->mu);
-            // cancelled running requests leave at this boundary
-            for (auto it = s->running.begin(); it != s->running.end();) {
-                if ((*it)->cancel) {
-                    release_request(s, **it);
-                    (*it)->state = TLB_REQ_CANCELLED;
-                    (*it)->done = Clock::now();
-                    it = s->running.erase(it);
-                    composition_changed = true;
-                    s->cv_done.notify_all();
-                } else {
-                    ++it;
-                }
-            }
-            run = s->running;
         }
         if (run.empty()) continue;
-        if (composition_changed) {
-            std::vector<tlb_ctx*> ctxs;
-            for (auto& r : run) ctxs.push_back(r->ctx);
-            const tlb_status bst = tlb_batch_set(s->batch, ctxs.data(), int(ctxs.size()));
-            if (bst != TLB_OK) {
-                std::lock_guard<std::mutex> lk(s->mu);
-                const std::string why = tlb_batch_last_error(s->batch);
-                for (auto& r : run) {
-                    release_request(s, *r);
-                    r->state = TLB_REQ_FAILED;
-                    r->status = bst;
-                    r->error = why;
-                    r->done = Clock::now();
-                    ++s->failed;
-                }
-                s->running.clear();
-                s->cv_done.notify_all();
-                continue;
-            }
-            composition_changed = false;
-        }
-        int64_t q = s->quantum;
-        double nodes = 0.0;
-        for (auto& r : run) {
-            q = std::min(q, r->remaining);
-            nodes += double(r->nx) * r->ny;
-        }
-        const auto t0 = Clock::now();
-        tlb_status st = tlb_batch_step(s->batch, q);
+        // (3) after the quantum
         if (st == TLB_OK) st = tlb_batch_sync(s->batch);
         const double dt = std::chrono::duration<double>(Clock::now() - t0).count();
-        std::vector<std::shared_ptr<Request>> finished;
-        {
-            std::lock_guard<std::mutex> lk(s->mu);
-            s->busy_s += dt;
-            s->node_steps += nodes * double(q);
-            for (auto& r : run) {
-                r->remaining -= q;
-                if (r->remaining <= 0 || st != TLB_OK) finished.push_back(r);
-            }
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->busy_s += dt;
+        s->node_steps += nodes * double(q);
+        for (auto& r : run) {
+            r->remaining -= q;
+            r->since_check += q;
         }
-        for (auto& r : finished) {
-            const bool ok = st == TLB_OK && finish_request(s, *r);
-            std::lock_guard<std::mutex> lk(s->mu);
-            release_request(s, *r);
-            r->done = Clock::now();
-            r->state = ok ? TLB_REQ_DONE : TLB_REQ_FAILED;
-            if (!ok && st != TLB_OK) r->status = st;
-            if (!ok && r->error.empty()) r->error = tlb_batch_last_error(s->batch);
-            if (ok) ++s->completed;
-            else ++s->failed;
-            s->running.erase(std::remove(s->running.begin(), s->running.end(), r), s->running.end());
-            composition_changed = true;
-            s->cv_done.notify_all();
+        if (st == TLB_OK)
+            for (int i : checked) {
+                run[size_t(i)]->since_check = 0;
+                if (s->health[4 * i + 3] != 0.0) {
+                    run[size_t(i)]->status = TLB_EDIVERGED;
+                    run[size_t(i)]->error = "diverged (NaN/Inf in c1, c2, ux or uy)";
+                }
+            }
+        for (auto& r : run) {
+            if (st != TLB_OK) {
+                r->status = st;
+                r->error = tlb_batch_last_error(s->batch);
+            }
+            if (r->remaining <= 0 || r->status != TLB_OK) {
+                to_finish.push_back(r);
+                s->running.erase(std::remove(s->running.begin(), s->running.end(), r),
+                                 s->running.end());
+                composition_changed = true;
+            }
         }
     }
     // shutdown: release everything still held
     std::lock_guard<std::mutex> lk(s->mu);
     const auto now = Clock::now();
-    for (auto& r : s->running) {
-        release_request(s, *r);
-        r->state = TLB_REQ_CANCELLED;
-        r->done = now;
+    for (auto* list : {&s->running, &to_finish, &ready}) {
+        for (auto& r : *list) {
+            release_request(s, *r);
+            r->state = TLB_REQ_CANCELLED;
+            r->done = now;
+        }
+        list->clear();
     }
-    s->running.clear();
     for (auto& r : s->queue) {
         r->state = TLB_REQ_CANCELLED;
         r->done = now;
@@ -382,7 +439,19 @@ tlb_status tlb_server_create(void* dev_arena, size_t arena_bytes, int max_slots,
     s->stream = static_cast<hipStream_t>(hip_stream);
     s->alloc.reset(arena_bytes);
     s->alloc.alloc(table, &s->table_off);
+    if (hipStreamCreateWithFlags(&s->io, hipStreamNonBlocking) != hipSuccess) {
+        delete s;
+        return sfail(nullptr, TLB_EDEVICE, "I/O stream");
+    }
+    if (hipHostMalloc(reinterpret_cast<void**>(&s->health), size_t(max_slots) * 4 * sizeof(double)) !=
+        hipSuccess) {
+        (void)hipStreamDestroy(s->io);
+        delete s;
+        return sfail(nullptr, TLB_ENOMEM, "pinned health words");
+    }
     if (tlb_batch_create(max_slots, s->arena + s->table_off, table, s->stream, &s->batch) != TLB_OK) {
+        (void)hipHostFree(s->health);
+        (void)hipStreamDestroy(s->io);
         delete s;
         return sfail(nullptr, TLB_EDEVICE, "batch table");
     }
@@ -529,7 +598,17 @@ void tlb_server_destroy(tlb_server* s) {
     s->cv_work.notify_all();
     if (s->worker.joinable()) s->worker.join();
     tlb_batch_destroy(s->batch);
+    (void)hipStreamSynchronize(s->io);
+    (void)hipStreamDestroy(s->io);
+    (void)hipHostFree(s->health);
     delete s;
+}
+
+tlb_status tlb_server_set_check_steps(tlb_server* s, int64_t steps) {
+    if (!s || steps <= 0) return sfail(s, TLB_EINVAL, "null server or check interval <= 0");
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->check_steps = steps;
+    return TLB_OK;
 }
 
 }  // extern "C"

@@ -14,9 +14,10 @@ import numpy as np
 import torch  # noqa: F401  (loads the HIP runtime before libtlb binds to it)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libtlb.so")
+# TLB_LIBRARY selects another build of the same library (the host-sanitized one)
+LIB_PATH = os.environ.get("TLB_LIBRARY") or os.path.join(_HERE, "libtlb.so")
 if not os.path.exists(LIB_PATH):
-    raise ImportError("libtlb.so is not built: run python -m paper_1710_09534_amd.build")
+    raise ImportError("%s is not built: run python -m paper_1710_09534_amd.build" % LIB_PATH)
 
 TLB_OK, TLB_EINVAL, TLB_EPARAM, TLB_ENOMEM, TLB_EDEVICE, TLB_EDIVERGED, TLB_ESTATE, TLB_EBUSY = (
     0, -1, -2, -3, -4, -5, -6, -7)
@@ -97,6 +98,7 @@ _SIGS = {
     "tlb_batch_sync": (C.c_int, [_vp]),
     "tlb_batch_last_error": (C.c_char_p, [_vp]),
     "tlb_batch_destroy": (None, [_vp]),
+    "tlb_server_set_check_steps": (C.c_int, [_vp, C.c_int64]),
     "tlb_server_create": (C.c_int, [_vp, C.c_size_t, C.c_int, C.c_int, C.c_int64, _vp,
                                     C.POINTER(_vp)]),
     "tlb_server_submit": (C.c_int, [_vp, C.POINTER(tlb_request), C.POINTER(C.c_uint64)]),
@@ -493,6 +495,9 @@ class Server:
             raise TlbError(st, lib.tlb_server_last_error(None).decode())
         self.h = h
         self._size = {}   # request id -> (nx, ny): the library writes that many nodes per field
+
+    def set_check_steps(self, steps: int):
+        self._check(lib.tlb_server_set_check_steps(self.h, int(steps)))
 
     def _check(self, st):
         if st != TLB_OK:

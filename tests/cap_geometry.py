@@ -39,3 +39,50 @@ def de_gennes(R, theta_deg):
     te = math.radians(theta_deg)
     k = math.sqrt((math.pi / 2) / (te - math.sin(te) * math.cos(te)))
     return 2 * R * k * math.sin(te), R * k * (1 - math.cos(te))
+
+
+def contour_points(c, level=0.5):
+    """Points of the c = level contour: crossings along every row and every
+    column of the lattice, by linear interpolation between neighbours."""
+    import numpy as np
+    ny, nx = c.shape
+    pts = []
+    for y in range(ny):
+        row = c[y]
+        for x in range(nx - 1):
+            a, b = row[x], row[x + 1]
+            if (a - level) * (b - level) < 0:
+                pts.append((x + (level - a) / (b - a), float(y)))
+    for x in range(nx):
+        col = c[:, x]
+        for y in range(ny - 1):
+            a, b = col[y], col[y + 1]
+            if (a - level) * (b - level) < 0:
+                pts.append((float(x), y + (level - a) / (b - a)))
+    return np.array(pts)
+
+
+def circle_fit(c, y_wall=0.5, exclude=4.0):
+    """Second estimate of the contact angle: a circle fitted to the c = 0.5
+    contour points higher than `exclude` above the wall surface (the cap away
+    from the wall's diffuse layer), least squares in the algebraic form
+    x^2 + y^2 + a x + b y + d = 0 refined by Gauss-Newton on the geometric
+    distances; the angle inside the drop where that circle meets the wall
+    line, arccos(-(y_c - y_wall) / r).  Returns (theta in degrees, x_c, y_c, r)."""
+    import numpy as np
+    pts = contour_points(c)
+    pts = pts[pts[:, 1] >= y_wall + exclude]
+    x, y = pts[:, 0], pts[:, 1]
+    A = np.c_[x, y, np.ones_like(x)]
+    a, b, d = np.linalg.lstsq(A, -(x * x + y * y), rcond=None)[0]
+    xc, yc = -a / 2, -b / 2
+    r = math.sqrt(xc * xc + yc * yc - d)
+    for _ in range(20):
+        dx, dy = x - xc, y - yc
+        rho = np.hypot(dx, dy)
+        J = np.c_[-dx / rho, -dy / rho, -np.ones_like(rho)]
+        step = np.linalg.lstsq(J, -(rho - r), rcond=None)[0]
+        xc, yc, r = xc + step[0], yc + step[1], r + step[2]
+        if np.abs(step).max() < 1e-12:
+            break
+    return math.degrees(math.acos(-(yc - y_wall) / r)), xc, yc, r

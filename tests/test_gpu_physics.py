@@ -143,27 +143,37 @@ def test_lens_parity(tlb):
     assert all(v <= 1e-12 for v in d.values()), d
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("R,steps,precision", [(24.0, 48000, "fp64"), (24.0, 48000, "fp32"),
+                                               (32.0, 72000, "fp64"), (48.0, 96000, "fp64")])
 @pytest.mark.parametrize("theta", [60.0, 120.0])
-def test_de_gennes_cap_at_radius_24(tlb, theta, precision):
-    """A sessile drop the size of the paper's two-drop layout (a half disc
-    of radius 24 on a wall of contact angle theta) relaxes to the circular
-    cap of Eq. 47 of the same area: L_s = 66.48, H_d = 19.19 at 60 deg and
-    L_s = 32.77, H_d = 28.38 at 120 deg.  Measured theta_n within 3 deg,
-    L_s and H_d within 6 % (the bounds of the oracle's R = 14 test).  The
-    measured angles, 62.3 and 118.6 deg, lie closer to the prescribed ones
-    than at R = 14 (62.6 and 117.6 deg): the diffuse-interface offset shrinks
-    as R / D grows."""
-    from cap_geometry import de_gennes, measure
-    R = 24.0
+def test_de_gennes_cap(tlb, theta, R, steps, precision):
+    """A sessile drop (a half disc of radius R on a wall of contact angle
+    theta, lattice 8R x 4R) relaxes to the circular cap of Eq. 47 of the same
+    area; at R = 24 (the paper's two-drop layout) that cap has L_s = 66.48,
+    H_d = 19.19 at 60 deg and L_s = 32.77, H_d = 28.38 at 120 deg.  Two
+    estimates of the angle: theta_n = 2 arctan(2 H_d / L_s) from the c = 0.5
+    contour (Sec. III.A) and a circle fitted to the contour away from the
+    wall; both within 1 deg of theta, L_s and H_d within 3 %.  The drop must
+    be relaxed: at R = 24 the angle reads 62.3 / 118.6 deg after 12000 steps,
+    59.7 / 119.4 after 48000 and stays there to 144000 steps; the relaxation
+    time grows with R (R = 48: 68.6 / 113.5 after 12000 steps, 59.7 / 119.9
+    after 72000).  Measured after the steps used here: theta_n 59.7 / 119.4
+    (R = 24), 59.6 / 119.7 (R = 32), 59.7 / 119.9 (R = 48)."""
+    from cap_geometry import circle_fit, de_gennes, measure
     Ls_th, Hd_th = de_gennes(R, theta)
-    quoted = {60.0: (66.48, 19.19), 120.0: (32.77, 28.38)}[theta]
-    assert abs(Ls_th - quoted[0]) < 0.01 and abs(Hd_th - quoted[1]) < 0.01
-    p = W.reduction_case(nx=192, ny=96, R=R, theta13=theta, sigma=(1e-2, 1e-2, 1e-2), noise=0)
+    if R == 24.0:
+        quoted = {60.0: (66.48, 19.19), 120.0: (32.77, 28.38)}[theta]
+        assert abs(Ls_th - quoted[0]) < 0.01 and abs(Hd_th - quoted[1]) < 0.01
+    nx, ny = int(8 * R), int(4 * R)
+    p = W.reduction_case(nx=nx, ny=ny, R=R, theta13=theta, sigma=(1e-2, 1e-2, 1e-2), noise=0)
+    print("case de Gennes R=%g theta=%g %s %dx%d steps=%d" % (R, theta, precision, nx, ny, steps),
+          flush=True)
     g = tlb.from_problem(p, precision)
-    g.step(12000)
-    th_n, Ls, Hd = measure(g.read_fields()["c1"])
-    print("theta %g %s: theta_n %.2f  L_s %.2f (%.2f)  H_d %.2f (%.2f)"
-          % (theta, precision, th_n, Ls, Ls_th, Hd, Hd_th), flush=True)
-    assert abs(th_n - theta) < 3.0
-    assert abs(Ls - Ls_th) < 0.06 * Ls_th and abs(Hd - Hd_th) < 0.06 * Hd_th
+    g.step(steps)
+    c1 = g.read_fields()["c1"]
+    th_n, Ls, Hd = measure(c1)
+    th_c = circle_fit(c1)[0]
+    print("theta %g R %g %s: theta_n %.2f circle %.2f  L_s %.2f (%.2f)  H_d %.2f (%.2f)"
+          % (theta, R, precision, th_n, th_c, Ls, Ls_th, Hd, Hd_th), flush=True)
+    assert abs(th_n - theta) <= 1.0 and abs(th_c - theta) <= 1.0
+    assert abs(Ls - Ls_th) < 0.03 * Ls_th and abs(Hd - Hd_th) < 0.03 * Hd_th

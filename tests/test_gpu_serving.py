@@ -98,3 +98,30 @@ def test_cancel_and_failure_isolation(tlb):
     ref = solo(tlb, p0, "fp64")
     assert np.array_equal(f["c1"], ref["c1"])
     srv.close()
+
+
+def test_diverged_request_fails_early(tlb):
+    """A request driven unstable by an absurd body force fails at the first
+    periodic health check after it diverges, long before its step budget,
+    while a well-posed request in the same mix finishes with its solo result."""
+    import time
+    probs = mix(2)
+    bad = dict(probs[1])
+    bad["fluid"] = dict(bad["fluid"], gravity=[0.0, -50.0])
+    srv = tlb.Server(1 << 30, max_slots=4, precision="fp32", quantum=50)
+    srv.set_check_steps(100)
+    t0 = time.perf_counter()
+    bad_id = srv.submit(bad, 10 ** 8)          # would take hours if it ran to the end
+    ok_id = srv.submit(probs[0], 300)
+    srv.wait(bad_id, 120.0)
+    assert srv.poll(bad_id) == tlb.TLB_REQ_FAILED
+    assert time.perf_counter() - t0 < 60.0
+    with pytest.raises(tlb.TlbError) as e:
+        srv.result(bad_id, bad["nx"], bad["ny"])
+    assert e.value.status == tlb.TLB_EDIVERGED
+    srv.wait(ok_id, 120.0)
+    assert srv.poll(ok_id) == tlb.TLB_REQ_DONE
+    f, _ = srv.result(ok_id, probs[0]["nx"], probs[0]["ny"])
+    ref = solo(tlb, dict(probs[0], steps=300), "fp32")
+    assert np.array_equal(f["c1"], ref["c1"])
+    srv.close()

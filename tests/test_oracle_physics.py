@@ -132,16 +132,34 @@ def test_laplace_law(R, n):
 @pytest.mark.parametrize("theta", [60.0, 120.0])
 def test_de_gennes_cap(theta):
     """A sessile drop relaxes to the circular cap of Eq. 47 with the
-    prescribed angle: theta_n within 3 deg, L_s and H_d within 6 %."""
+    prescribed angle.  R = 14 (R / D = 3.5) after 24000 steps: theta_n 59.8 /
+    118.6 deg, the circle-fit estimate 59.8 / 119.0 (after 6000 steps the
+    drop is still relaxing: 62.6 / 117.6); bars 1.5 deg, L_s and H_d within
+    4 %."""
     R = 14.0
     p = W.reduction_case(nx=96, ny=48, R=R, theta13=theta, sigma=(1e-2, 1e-2, 1e-2), noise=0)
-    s = _run(p, 6000)
-    from cap_geometry import de_gennes, measure
+    s = _run(p, 24000)
+    from cap_geometry import circle_fit, de_gennes, measure
     c1 = s.fields()["c1"]
     th_n, Ls, Hd = measure(c1)
+    th_c = circle_fit(c1)[0]
     Ls_th, Hd_th = de_gennes(R, theta)
-    assert abs(th_n - theta) < 3.0, (th_n, theta)
-    assert abs(Ls - Ls_th) < 0.06 * Ls_th and abs(Hd - Hd_th) < 0.06 * Hd_th, (Ls, Ls_th, Hd, Hd_th)
+    assert abs(th_n - theta) <= 1.5 and abs(th_c - theta) <= 1.5, (th_n, th_c, theta)
+    assert abs(Ls - Ls_th) < 0.04 * Ls_th and abs(Hd - Hd_th) < 0.04 * Hd_th, (Ls, Ls_th, Hd, Hd_th)
+
+
+def test_circle_fit_recovers_a_cap():
+    """The circle-fit estimate on a synthetic tanh cap of known geometry:
+    a disc of radius 20 centred 8 below the wall surface meets the wall at
+    arccos(8/20) = 66.4 deg, and one centred 8 above it at 113.6 deg."""
+    from cap_geometry import circle_fit
+    import math
+    for yc, want in ((0.5 - 8.0, math.degrees(math.acos(8.0 / 20.0))),
+                     (0.5 + 8.0, 180.0 - math.degrees(math.acos(8.0 / 20.0)))):
+        c = W.tanh_drop(128, 64, 64.0, yc, 20.0, 4.0)
+        c[0, :] = 0.0
+        th, xc, ycf, r = circle_fit(c)
+        assert abs(th - want) < 0.2 and abs(r - 20.0) < 0.1 and abs(ycf - yc) < 0.1, (th, want)
 
 
 def test_hydrostatic_pressure_in_stratified_layers():
