@@ -2,8 +2,8 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32]
                     [--workload cylinder_impact] [--only] [--no-cpu]
-                    [--no-serving] [--no-sweep] [--no-3d] [--only-3d] [--serving-full]
-                    [--copy-calibration MIB]
+                    [--no-serving] [--serving-slice] [--serving-fp16dev] [--serving-full]
+                    [--no-sweep] [--no-3d] [--only-3d] [--copy-calibration MIB]
 
 Workload: the compound-drop / cylinder-impact lattice, 1024 x 2048 nodes,
 staircase cylinder of radius 128 (We = 10, theta = 90 deg), FP32
@@ -457,8 +457,13 @@ def main():
     ap.add_argument("--no-3d", action="store_true", help="skip the three-dimensional leg")
     ap.add_argument("--only-3d", action="store_true",
                     help="run only the three-dimensional leg (--steps steps per precision)")
+    ap.add_argument("--serving-slice", action="store_true",
+                    help="serve a 120-request, 1000-4000-step slice of the stream instead of the "
+                         "whole 1000-request stream (seconds instead of about three minutes)")
+    ap.add_argument("--serving-fp16dev", action="store_true",
+                    help="also serve the stream with FP16-deviation storage (capacity, 0.7x load)")
     ap.add_argument("--serving-full", action="store_true",
-                    help="also serve the full 1000-request stream (several minutes)")
+                    help="serve only the whole stream (with --only: nothing else is timed)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB, 10 times (counter scale)")
     args = ap.parse_args()
@@ -534,22 +539,30 @@ def main():
     out["stream_reference"] = stream_reference(tlb, torch)
     if not args.only:
         out["configs"] = config_table(tlb, torch, cpu=not args.no_cpu)
-    if args.serving_full:
-        # the whole seeded stream of the serving workload: 1000 requests of
-        # 1000-20000 steps under a 200 GB arena (minutes of GPU time)
-        out["serving_full"] = serving_leg(tlb, torch, n_requests=1000, steps=(1000, 20000),
-                                          arena_gb=200.0, slots=128, quantum=500,
-                                          calibrate_sequential=True)
-        print("# serving (full stream): %s" % out["serving_full"], file=sys.stderr, flush=True)
+    # the whole seeded stream of the serving workload: 1000 requests of
+    # 1000-20000 steps under a 200 GB arena, 128 slots, at 0.7x and 1.2x the
+    # measured capacity, against the same stream served one request at a
+    # time by the plain FP64 path (service times from per-size-class
+    # measurements of that path)
+    full = dict(n_requests=1000, steps=(1000, 20000), arena_gb=200.0, slots=128, quantum=500,
+                calibrate_sequential=True)
     if not (args.only or args.no_serving):
         out["batching"] = batching_leg(tlb, torch)
         print("# batching: %s" % out["batching"], file=sys.stderr, flush=True)
-        out["serving"] = serving_leg(tlb, torch)
+    if args.serving_full or not (args.only or args.no_serving):
+        if args.serving_slice and not args.serving_full:
+            out["serving"] = serving_leg(tlb, torch)
+        else:
+            out["serving"] = serving_leg(tlb, torch, **full)
+            out["serving"]["stream"] = "full: 1000 requests, 1000-20000 steps, 200 GB arena"
         print("# serving: %s" % out["serving"], file=sys.stderr, flush=True)
-        # the same stream with FP16-deviation storage: capacity and 0.7x load
-        out["serving_fp16dev"] = serving_leg(tlb, torch, precision="fp16dev", loads=(0.7,),
-                                             sequential=False)
-        print("# serving fp16dev: %s" % out["serving_fp16dev"], file=sys.stderr, flush=True)
+        if args.serving_fp16dev:
+            kw = dict(full, calibrate_sequential=False)
+            if args.serving_slice and not args.serving_full:
+                kw = {}
+            out["serving_fp16dev"] = serving_leg(tlb, torch, precision="fp16dev", loads=(0.7,),
+                                                 sequential=False, **kw)
+            print("# serving fp16dev: %s" % out["serving_fp16dev"], file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(problem)
     print(json.dumps(out), flush=True)

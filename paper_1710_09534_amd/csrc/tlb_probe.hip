@@ -4,7 +4,7 @@
 // peak the step reaches can be read against what this device sustains for
 // the same access pattern.
 //   kind 0: copy of 16-byte words (dwordx4 loads and stores), grid-stride
-//           over the buffer, non-temporal stores;
+//           over the buffer, four words per lane in flight, non-temporal;
 //   kind 1: the step kernel's access shape: workgroups of four row waves,
 //           one lane per column of a 64-column strip of tile_rows rows, each
 //           node reads 31 FP32 planes (27 population planes at x - e_k of the
@@ -23,11 +23,20 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 constexpr int PEX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 constexpr int PEY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 
+// four independent 16-byte words per lane in flight per iteration (loads
+// first, then stores), non-temporal on both sides
 __global__ __launch_bounds__(256) void copy16_kernel(const f4* __restrict__ src,
                                                      f4* __restrict__ dst, size_t n) {
     const size_t stride = size_t(gridDim.x) * blockDim.x;
-    for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
-        __builtin_nontemporal_store(src[i], &dst[i]);
+    size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        f4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = __builtin_nontemporal_load(&src[i + u * stride]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) __builtin_nontemporal_store(v[u], &dst[i + u * stride]);
+    }
+    for (; i < n; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(&src[i]), &dst[i]);
 }
 
 __global__ __launch_bounds__(256) void soa31_kernel(const float* __restrict__ src,
@@ -80,7 +89,7 @@ extern "C" tlb_status tlb_probe_bandwidth(int kind, int nx, int ny, int tile_row
     }
     auto launch = [&]() {
         if (kind == 0) {
-            hipLaunchKernelGGL(copy16_kernel, dim3(4096), dim3(256), 0, s,
+            hipLaunchKernelGGL(copy16_kernel, dim3(2048), dim3(256), 0, s,
                                static_cast<const f4*>(dev_src), static_cast<f4*>(dev_dst),
                                bytes / 16);
         } else {
