@@ -174,6 +174,15 @@ def batching_leg(tlb, torch, precision="fp32", n_lattices=256, size=64, steps=20
     b.step(steps)
     b.sync()
     t_batch = time.perf_counter() - t0
+    # the same batch with strip heights from the batch autotuner
+    rows = b.autotune_rows(10)
+    b.use_graph(50)
+    b.step(50)
+    b.sync()
+    t0 = time.perf_counter()
+    b.step(steps)
+    b.sync()
+    t_tuned = time.perf_counter() - t0
     del b, solvers
     solvers = [tlb.from_problem(p, "fp64") for p in probs]
     for s in solvers:
@@ -188,6 +197,8 @@ def batching_leg(tlb, torch, precision="fp32", n_lattices=256, size=64, steps=20
     nodes = n_lattices * size * size
     return {"lattices": n_lattices, "size": "%dx%d" % (size, size), "precision": precision,
             "steps": steps, "one_at_a_time_mlups": round(nodes * steps / t_solo / 1e6, 1),
+            "autotuned_rows": rows,
+            "batched_autotuned_mlups": round(nodes * steps / t_tuned / 1e6, 1),
             "batched_mlups": round(nodes * steps / t_batch / 1e6, 1),
             "speedup": round(t_solo / t_batch, 2),
             "one_at_a_time_fp64_mlups": round(nodes * steps / t_fp64 / 1e6, 1),

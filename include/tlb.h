@@ -260,6 +260,17 @@ tlb_status tlb_batch_use_graph(tlb_batch* batch, int steps);
 /* advances every member by nsteps, asynchronously on the batch stream */
 tlb_status tlb_batch_step(tlb_batch* batch, int64_t nsteps);
 tlb_status tlb_batch_sync(tlb_batch* batch);
+/* Strip heights of the members (the step kernel's tile shape), tuned for the
+ * batched launch: members of equal height form a size class, and one pass
+ * over the classes, tallest first, gives each class the height among 16,
+ * 24, 32, 48, 64, 96 and 128 rows (at most the lattice's) that makes the
+ * batched step shortest, each candidate timed over steps_per_candidate
+ * batched steps (HIP events on the batch stream).  Advances every member by
+ * those steps (results do not depend on strip heights, bitwise), re-registers
+ * the members and drops a captured graph (call tlb_batch_use_graph again).
+ * best_rows (nullable) receives the tallest class's height.  TLB_ESTATE
+ * before tlb_batch_set. */
+tlb_status tlb_batch_autotune_rows(tlb_batch* batch, int steps_per_candidate, int* best_rows);
 const char* tlb_batch_last_error(const tlb_batch* batch);
 void       tlb_batch_destroy(tlb_batch* batch);
 

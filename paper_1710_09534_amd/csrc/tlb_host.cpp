@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <functional>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -864,6 +865,77 @@ tlb_status tlb_batch_sync(tlb_batch* b) {
     if (!b) return bfail(b, TLB_EINVAL, "null batch");
     hipError_t e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return bfail(b, TLB_EDEVICE, std::string("batch sync: ") + hipGetErrorString(e));
+    return TLB_OK;
+}
+
+tlb_status tlb_batch_autotune_rows(tlb_batch* b, int steps_per_candidate, int* best_rows) {
+    if (!b || steps_per_candidate <= 0) return bfail(b, TLB_EINVAL, "bad arguments");
+    if (b->ctxs.empty()) return bfail(b, TLB_ESTATE, "tlb_batch_set must precede autotune");
+    static const int cand[] = {16, 24, 32, 48, 64, 96, 128};
+    const std::vector<tlb_ctx*> members = b->ctxs;
+    // size classes: members of the same height share a strip height
+    std::vector<int> heights;
+    for (tlb_ctx* c : members)
+        if (std::find(heights.begin(), heights.end(), c->ny) == heights.end())
+            heights.push_back(c->ny);
+    std::sort(heights.begin(), heights.end(), std::greater<int>());
+    std::vector<int> rows(heights.size());
+    for (size_t h = 0; h < heights.size(); ++h) {
+        rows[h] = members[0]->grid.tile_rows;
+        for (tlb_ctx* c : members)
+            if (c->ny == heights[h]) rows[h] = c->grid.tile_rows;
+    }
+    auto apply = [&]() -> tlb_status {
+        for (tlb_ctx* c : members) {
+            const size_t h = size_t(std::find(heights.begin(), heights.end(), c->ny) - heights.begin());
+            tlb_status st = tlb_set_tile_rows(c, rows[h]);
+            if (st != TLB_OK) return bfail(b, st, std::string("set rows: ") + c->err);
+        }
+        return tlb_batch_set(b, members.data(), int(members.size()));
+    };
+    auto time_batch = [&](double* ms) -> tlb_status {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        hipError_t e = hipEventCreate(&e0);
+        if (e == hipSuccess) e = hipEventCreate(&e1);
+        if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+        tlb_status st = e == hipSuccess ? tlb_batch_step(b, steps_per_candidate) : TLB_EDEVICE;
+        if (st == TLB_OK) {
+            e = hipEventRecord(e1, b->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float f = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&f, e0, e1);
+            *ms = double(f) / steps_per_candidate;
+            if (e != hipSuccess) st = TLB_EDEVICE;
+        }
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (st == TLB_EDEVICE) return bfail(b, st, "autotune timing");
+        return st;
+    };
+    // one pass of coordinate descent over the size classes, tallest first:
+    // every member of a class takes the candidate that gives the shortest
+    // batched step with the other classes at their current strip heights
+    for (size_t h = 0; h < heights.size(); ++h) {
+        const int limit = std::max(16, (heights[h] + 3) / 4 * 4);
+        int best = rows[h];
+        double best_ms = 1e30;
+        for (int r : cand) {
+            if (r > limit) break;
+            rows[h] = r;
+            tlb_status st = apply();
+            double ms = 0.0;
+            if (st == TLB_OK) st = time_batch(&ms);
+            if (st != TLB_OK) return st;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = r;
+            }
+        }
+        rows[h] = best;
+    }
+    tlb_status st = apply();
+    if (st != TLB_OK) return st;
+    if (best_rows) *best_rows = rows.empty() ? 0 : rows[0];
     return TLB_OK;
 }
 

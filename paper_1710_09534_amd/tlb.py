@@ -95,6 +95,7 @@ _SIGS = {
     "tlb_batch_set": (C.c_int, [_vp, C.POINTER(_vp), C.c_int]),
     "tlb_batch_use_graph": (C.c_int, [_vp, C.c_int]),
     "tlb_batch_step": (C.c_int, [_vp, C.c_int64]),
+    "tlb_batch_autotune_rows": (C.c_int, [_vp, C.c_int, C.POINTER(C.c_int)]),
     "tlb_batch_sync": (C.c_int, [_vp]),
     "tlb_batch_last_error": (C.c_char_p, [_vp]),
     "tlb_batch_destroy": (None, [_vp]),
@@ -347,6 +348,11 @@ class Batch:
 
     def step(self, n: int):
         self._check(lib.tlb_batch_step(self.h, int(n)))
+
+    def autotune_rows(self, steps_per_candidate: int = 20) -> int:
+        best = C.c_int()
+        self._check(lib.tlb_batch_autotune_rows(self.h, int(steps_per_candidate), C.byref(best)))
+        return best.value
 
     def sync(self):
         self._check(lib.tlb_batch_sync(self.h))

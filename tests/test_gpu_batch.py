@@ -88,3 +88,27 @@ def test_autotune_keeps_the_trajectory(tlb):
     b.set_check_interval(0)
     b.step(n)
     assert np.array_equal(a.read_populations(), b.read_populations())
+
+
+def test_batch_autotune_keeps_the_trajectory(tlb):
+    """The batch autotuner (one strip height per size class, chosen by timing
+    the batched launch) advances every member but leaves its trajectory
+    bitwise that of the member stepped alone for the same number of steps,
+    and gives each class a legal strip height."""
+    probs = problems()
+    members = [tlb.from_problem(p, "fp32") for p in probs]
+    for s in members:
+        s.set_check_interval(0)
+    b = tlb.Batch(8)
+    b.set(members)
+    best = b.autotune_rows(3)
+    b.step(7)
+    b.sync()
+    assert best % 4 == 0 and 16 <= best <= 128
+    for p, s in zip(probs, members):
+        n = s.step_count
+        assert n > 7
+        ref = tlb.from_problem(p, "fp32")
+        ref.set_check_interval(0)
+        ref.step(n)
+        assert np.array_equal(s.read_populations(), ref.read_populations()), p["name"]
