@@ -93,6 +93,25 @@ def time_precision(tlb, torch, problem, precision, steps, warmup):
     return dt, kms, m
 
 
+def host_inclusive(tlb, torch, problem, precision, steps):
+    """The same workload as a whole solve through the C ABI's host-side calls:
+    from the host arrays (context creation, geometry, initial fields copied
+    over PCIe, equilibrium initialisation) through `steps` steps to all ten
+    fields copied back to host memory, timed on the host clock.  Not the
+    benchmark's value, which has the inputs resident in HBM."""
+    n = problem["nx"] * problem["ny"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s = tlb.from_problem(problem, precision)
+    s.set_check_interval(100)
+    s.step(steps)
+    s.read_fields()
+    dt = time.perf_counter() - t0
+    del s
+    return {"precision": precision, "steps": steps, "seconds": round(dt, 4),
+            "mlups": round(n * steps / dt / 1e6, 1)}
+
+
 def bw_sweep_leg(tlb, torch, sizes=((1024, 2048), (2048, 2048), (4096, 4096)), steps=500):
     """The cylinder layout without a drop at three sizes and every storage
     precision: step-kernel time from HIP events on the solver's stream over
@@ -546,6 +565,7 @@ def main():
         out["bw_sweep"] = bw_sweep_leg(tlb, torch)
     if not (args.only or args.no_3d):
         out["d3q19"] = leg_3d(tlb, torch)
+    out["host_inclusive"] = host_inclusive(tlb, torch, problem, args.precision, args.steps)
     out["copy_reference"] = copy_reference(torch)
     out["stream_reference"] = stream_reference(tlb, torch)
     if not args.only:
