@@ -8,9 +8,9 @@
   of the FP64 run;
 * binary drops on a substrate (256 x 128, densities 10/5/1) in FP32 after 2000
   steps: order parameters within 1e-4;
-* the 1024 x 2048 cylinder impact in FP32 for 100 steps, in the launch
-  configuration of the benchmark: order parameters within 1e-4, velocity
-  within 1e-6;
+* the 1024 x 2048 cylinder impact in FP32 and FP16-dev for 100 steps, in the
+  launch configuration of the benchmark: order parameters within 1e-4,
+  velocity within 1e-6;
 * the reduction-consistency variant of the 64 x 64 case on the GPU in FP64:
   with phase 2 absent, sigma_12 = 1.5e-3 and sigma_23 = 1.2e-3 leave c1 equal
   to the run with equal tensions within 1e-12 after 1000 steps (Sec. II.B,
@@ -140,15 +140,21 @@ def test_binary_drops_256x128_fp32(tlb):
     assert e["c1"] <= 1e-4 and e["c2"] <= 1e-4 and e["c3"] <= 1e-4, e
 
 
-def test_cylinder_impact_1024x2048_fp32(tlb):
+@pytest.fixture(scope="module")
+def cylinder_ref():
     p = W.cylinder_impact(We=10, theta=90)
-    _say("case %s fp32 100 steps, 64-row strips" % p["name"])
-    fo = _oracle(p, 100).fields()
-    g = tlb.from_problem(p, "fp32")
+    return p, _oracle(p, 100).fields()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16dev"])
+def test_cylinder_impact_1024x2048_reduced_precision(tlb, cylinder_ref, precision):
+    p, fo = cylinder_ref
+    _say("case %s %s 100 steps, 64-row strips" % (p["name"], precision))
+    g = tlb.from_problem(p, precision)
     g.set_tile_rows(64)
     g.step(100)
     e = _errors(g.read_fields(), fo)
-    _say("cylinder impact 1024x2048 fp32 errors after 100 steps: %s" % _fmt(e))
+    _say("cylinder impact 1024x2048 %s errors after 100 steps: %s" % (precision, _fmt(e)))
     assert e["c1"] <= 1e-4 and e["c2"] <= 1e-4 and e["c3"] <= 1e-4, e
     assert e["ux"] <= 1e-6 and e["uy"] <= 1e-6, e
 
