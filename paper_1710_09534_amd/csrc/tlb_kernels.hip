@@ -191,6 +191,10 @@ __device__ __forceinline__ void phase_a(Smem<P, TY>& sm, const Grid& g,
     }
 }
 
+// 1/x: FP32 arithmetic uses the hardware reciprocal (1 ulp), FP64 divides
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
 // Macroscopic state of one interior node (phase C front half).
 template <typename R>
 struct NodeMacro {
@@ -286,14 +290,14 @@ __device__ __forceinline__ NodeMacro<R> node_macro(const Stencil<R>& s, const Co
         if (EY[k]) my += R(EY[k]) * gg[k];
         if (k) sum += gg[k];
     }
-    const R irho = R(1) / rho;
+    const R irho = recip(rho);
     const R ux = (mx + R(0.5) * fx) * irho;
     const R uy = (my + R(0.5) * fy) * irho;
     const R a = c.am1 * lm1 + c.am2 * lm2;
     const R uu = ux * ux + uy * uy;
     // c_s^2/(1-w0) = 3/5; s_0(u) = -w0 u.u/(2 c_s^2) = -(2/3) u.u
     const R p = R(0.6) * (sum + R(0.5) * (ux * grx + uy * gry) - rho * (R(2) / R(3)) * uu);
-    o.c1 = c1; o.c2 = c2; o.rho = rho; o.itg = R(1) / taug;
+    o.c1 = c1; o.c2 = c2; o.rho = rho; o.itg = recip(taug);
     o.mu1 = mu1; o.mu2 = mu2; o.ux = ux; o.uy = uy; o.p = p;
     o.grx = grx; o.gry = gry; o.fx = fx; o.fy = fy; o.fax = ux * a; o.fay = uy * a;
     o.am = a;
@@ -412,15 +416,16 @@ __device__ __forceinline__ void phase_b(Smem<P, TY>& sm, const Consts<typename T
 // (rows y-1..y+4) live in LDS rings, so every population is pulled once per
 // strip apart from the side halo and 4 rows per strip.
 //   phase A: row wave w forms c1, c2 of row Y+2+w from its prefetched
-//            pulls, issues the g / history loads of its phase-C row and then
-//            the pulls of row Y+6+w (next iteration); the halo wave does the
-//            same for the 16 halo nodes of rows Y+2..Y+5.  The loads complete
-//            while the workgroup runs phase B.
+//            pulls and issues the g / history loads of its phase-C row; the
+//            halo wave does the same for the 16 halo nodes of rows Y+2..Y+5
+//            and issues their next pulls.  The loads complete while the
+//            workgroup runs phase B.
 //   phase B: mu on rows Y+1..Y+4, and each node's solid-neighbour mask.
 //   phase C: row wave w updates row Y + ((w+2) & 3): waves 0, 1 the row they
 //            pulled in this iteration (still in registers), waves 2, 3 the
 //            row they pulled in the previous one (parked in a per-wave,
-//            double-buffered LDS stash).
+//            double-buffered LDS stash).  Before it collides, a row wave
+//            issues the pulls of row Y+6+w for the next iteration.
 // The row waves and the halo wave run separate loops with the same barrier
 // sequence, so the compiler's wait counts for each follow its own stores.
 // Memory is addressed through buffer resources: one 32-bit lane offset per
@@ -681,32 +686,47 @@ __device__ __forceinline__ void ring_mu(Ring<P>& sm, const Consts<typename Tr<P>
         c2r[q] = &sm.c2[sc[q] * RG::W + col];
         mr[q] = &sm.m[sc[q] * RG::W + col];
     }
-    unsigned mask = mr[1][0] ? kSelfBit : 0u;
+    // the whole 3x3 neighbourhood (material bytes and both c values) is read
+    // before anything depends on it, so the LDS latency is paid once
+    uint8_t mb[9];
+    R v1[9], v2[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        mb[k] = mr[EY[k] + 1][EX[k]];
+        v1[k] = c1r[EY[k] + 1][EX[k]];
+        v2[k] = c2r[EY[k] + 1][EX[k]];
+    }
+    unsigned mask = mb[0] ? kSelfBit : 0u;
 #pragma unroll
     for (int k = 1; k < 9; ++k) {
-        const unsigned mn = mr[EY[k] + 1][EX[k]];
+        const unsigned mn = mb[k];
         if (mn)
             mask |= ((F & kFeatVel) && ((c.nee >> mn) & 1u)) ? 1u << (kVelShift + k) : 1u << (k - 1);
     }
-    R mu1 = R(0), mu2 = R(0), mu3 = R(0);
-    if (!(mask & kSelfBit)) {
-        if (mask == 0) {
-            // bulk node: plain Laplacian (Eq. 20b)
-            const R a1 = c1r[1][0], a2 = c2r[1][0], a3 = R(1) - a1 - a2;
-            R l1 = R(0), l2 = R(0);
+    // the bulk form, plain Laplacian (Eq. 20b), is evaluated for every node
+    // (so that the reads above stay ahead of the mask) and replaced where the
+    // node is solid or has a solid neighbour
+    R mu1, mu2, mu3;
+    {
+        const R a1 = v1[0], a2 = v2[0], a3 = R(1) - a1 - a2;
+        R l1 = R(0), l2 = R(0);
 #pragma unroll
-            for (int k = 1; k < 9; ++k) {
-                l1 += wgt<R>(k) * (c1r[EY[k] + 1][EX[k]] - a1);
-                l2 += wgt<R>(k) * (c2r[EY[k] + 1][EX[k]] - a2);
-            }
-            l1 *= R(6);
-            l2 *= R(6);
-            const R l3 = -(l1 + l2);   // c3 = 1 - c1 - c2 at every node of the stencil
-            const R tri = R(2) * c.lamT * a1 * a2 * (R(1) - a1 - a2);
-            mu1 = c.k12D * (c.lam1 * a1 * (R(1) - a1) * (R(1) - R(2) * a1) - tri) - c.k34D * c.lam1 * l1;
-            mu2 = c.k12D * (c.lam2 * a2 * (R(1) - a2) * (R(1) - R(2) * a2) - tri) - c.k34D * c.lam2 * l2;
-            mu3 = c.k12D * (c.lam3 * a3 * (R(1) - a3) * (R(1) - R(2) * a3) - tri) - c.k34D * c.lam3 * l3;
-            lambda_term<R, (F & kFeatLam) != 0>(c, a1, a2, mu1, mu2, mu3);
+        for (int k = 1; k < 9; ++k) {
+            l1 += wgt<R>(k) * (v1[k] - a1);
+            l2 += wgt<R>(k) * (v2[k] - a2);
+        }
+        l1 *= R(6);
+        l2 *= R(6);
+        const R l3 = -(l1 + l2);   // c3 = 1 - c1 - c2 at every node of the stencil
+        const R tri = R(2) * c.lamT * a1 * a2 * (R(1) - a1 - a2);
+        mu1 = c.k12D * (c.lam1 * a1 * (R(1) - a1) * (R(1) - R(2) * a1) - tri) - c.k34D * c.lam1 * l1;
+        mu2 = c.k12D * (c.lam2 * a2 * (R(1) - a2) * (R(1) - R(2) * a2) - tri) - c.k34D * c.lam2 * l2;
+        mu3 = c.k12D * (c.lam3 * a3 * (R(1) - a3) * (R(1) - R(2) * a3) - tri) - c.k34D * c.lam3 * l3;
+        lambda_term<R, (F & kFeatLam) != 0>(c, a1, a2, mu1, mu2, mu3);
+    }
+    if (mask != 0) {
+        if (mask & kSelfBit) {
+            mu1 = mu2 = mu3 = R(0);
         } else {
             chem_pot<R, (F & kFeatVel) != 0, (F & kFeatLam) != 0>(c1r, c2r, mr, sm.mt, c, mu1,
                                                                   mu2, mu3);
@@ -974,8 +994,8 @@ __device__ __forceinline__ void step_tile(const Grid& g, const Consts<typename T
         int yo = 0;
 
         // phase A of iteration it: c of row Y+2+w from the prefetched pulls u,
-        // then the phase-C operands of iteration it, then the pulls for
-        // iteration it+1 into f
+        // then the phase-C operands of iteration it (and, in the prologue, the
+        // pulls for iteration 0 into f; later pulls are issued in phase C)
         auto phase_a = [&](int it, const R (&u1)[9], const R (&u2)[9], uint8_t um, R (&f1)[9],
                            R (&f2)[9], uint8_t& fm) {
             const int Y = y0 + 4 * it;
@@ -1016,14 +1036,17 @@ __device__ __forceinline__ void step_tile(const Grid& g, const Consts<typename T
                         hist, int(gon ? idx * 4u : kDiscard), int(q * hstride), 0));
             }
             __builtin_amdgcn_sched_barrier(0);
-            pull_f<P>(g, c, src, matr, gxl, wrapc(Y + 6 + w, g.ny), Y + 6 + w <= ylast, f1, f2, fm);
+            if (it < 0)
+                pull_f<P>(g, c, src, matr, gxl, wrapc(Y + 6 + w, g.ny), Y + 6 + w <= ylast, f1, f2,
+                          fm);
             __builtin_amdgcn_sched_barrier(0);
         };
 
-        // phase C of iteration it: row wave w updates row yo from u (waves 0, 1)
-        // or from the row it parked in the stash one iteration earlier (waves 2,
-        // 3, loaded into u, which phase A no longer needs)
-        auto phase_c = [&](int it, R (&u1)[9], R (&u2)[9]) {
+        // phase C of iteration it: row wave w issues the pulls for iteration
+        // it+1 into f, then updates row yo from u (waves 0, 1) or from the row
+        // it parked in the stash one iteration earlier (waves 2, 3, loaded
+        // into u, which phase A no longer needs)
+        auto phase_c = [&](int it, R (&u1)[9], R (&u2)[9], R (&f1)[9], R (&f2)[9], uint8_t& fm) {
             Stencil<R> s;
             const int sl[3] = {ring_slot(yo - 1, y0), ring_slot(yo, y0), ring_slot(yo + 1, y0)};
             const int ml[3] = {mu_slot(yo - 1, y0), mu_slot(yo, y0), mu_slot(yo + 1, y0)};
@@ -1045,6 +1068,13 @@ __device__ __forceinline__ void step_tile(const Grid& g, const Consts<typename T
                     u2[k] = sm.stash[(it - 1) & 1][w - 2][9 + k][lane];
                 }
             }
+            {
+                const int Y = y0 + 4 * it;
+                __builtin_amdgcn_sched_barrier(0);
+                pull_f<P>(g, c, src, matr, gxl, wrapc(Y + 6 + w, g.ny), Y + 6 + w <= ylast, f1, f2,
+                          fm);
+                __builtin_amdgcn_sched_barrier(0);
+            }
             node_update<P, F>(g, c, s, sm.mt, nb, idx, live, mask, u1, u2, gg, ho, dst, hist, hstride);
         };
 
@@ -1059,7 +1089,7 @@ __device__ __forceinline__ void step_tile(const Grid& g, const Consts<typename T
             __syncthreads();
             phase_b(it);
             __syncthreads();
-            phase_c(it, fb1, fb2);
+            phase_c(it, fb1, fb2, nf1, nf2, nm);
             // phase A of the next iteration (after the last one its loads
             // are all out of range)
             phase_a(it + 1, nf1, nf2, nm, fb1, fb2, mb);
@@ -1067,7 +1097,7 @@ __device__ __forceinline__ void step_tile(const Grid& g, const Consts<typename T
             __syncthreads();
             phase_b(it + 1);
             __syncthreads();
-            phase_c(it + 1, nf1, nf2);
+            phase_c(it + 1, nf1, nf2, fb1, fb2, mb);
             phase_a(it + 2, fb1, fb2, mb, nf1, nf2, nm);
         }
     } else {
@@ -1077,7 +1107,11 @@ __device__ __forceinline__ void step_tile(const Grid& g, const Consts<typename T
         int yo = 0;
 
         // phase A of iteration it: c of row Y+2+w from the prefetched pulls, then
-        // the phase-C operands of iteration it, then the pulls for iteration it+1
+        // the phase-C operands of iteration it.  The pulls for iteration it+1
+        // are issued at the start of phase C (in the prologue, it = -1, here):
+        // a row wave that issued them here, in one burst with the g / history
+        // loads, stalled on issue while the other waves waited at the barrier
+        // (FP32 111.7 -> 109.0 us per step on a 1024 x 2048 lattice).
         auto phase_a = [&](int it) {
             const int Y = y0 + 4 * it;
             const int sl = ring_slot(Y + 2 + w, y0) * RG::W + lane + 2;
@@ -1117,7 +1151,9 @@ __device__ __forceinline__ void step_tile(const Grid& g, const Consts<typename T
                         hist, int(gon ? idx * 4u : kDiscard), int(q * hstride), 0));
             }
             __builtin_amdgcn_sched_barrier(0);
-            pull_f<P>(g, c, src, matr, gxl, wrapc(Y + 6 + w, g.ny), Y + 6 + w <= ylast, nf1, nf2, nm);
+            if (it < 0)
+                pull_f<P>(g, c, src, matr, gxl, wrapc(Y + 6 + w, g.ny), Y + 6 + w <= ylast, nf1, nf2,
+                          nm);
             __builtin_amdgcn_sched_barrier(0);
         };
 
@@ -1153,6 +1189,13 @@ __device__ __forceinline__ void step_tile(const Grid& g, const Consts<typename T
                         cf1[k] = sm.stash[(it - 1) & 1][w - 2][k][lane];
                         cf2[k] = sm.stash[(it - 1) & 1][w - 2][9 + k][lane];
                     }
+                }
+                {
+                    const int Y = y0 + 4 * it;
+                    __builtin_amdgcn_sched_barrier(0);
+                    pull_f<P>(g, c, src, matr, gxl, wrapc(Y + 6 + w, g.ny), Y + 6 + w <= ylast, nf1,
+                              nf2, nm);
+                    __builtin_amdgcn_sched_barrier(0);
                 }
                 node_update<P, F>(g, c, s, sm.mt, nb, idx, live, mask, cf1, cf2, gg, ho, dst, hist,
                                   hstride);
