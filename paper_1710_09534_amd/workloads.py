@@ -351,6 +351,48 @@ def random_fields(nx, ny, seed=7, amp=0.2, geometry="channel", U=0.0, rho=(1.0, 
                     mats, c1, c2, ux, uy, steps=0)
 
 
+def random_obstacles(nx, ny, seed=3, n_obstacles=40, n_materials=6, amp=0.2, U=0.01,
+                     moving=True):
+    """The smooth random three-phase mixture of ``random_fields`` in a fully
+    periodic box scattered with small solid obstacles of ``n_materials``
+    wetting materials: single nodes, 2x2 blocks, one-node-thick bars, L shapes
+    and diagonal staircases, placed anywhere (so they touch each other, wrap
+    across the periodic seams and cross strip boundaries).  Each material's
+    contact angles are drawn until they are admissible; with ``moving`` every
+    other material moves at speed U along x or y.  For parity tests of the
+    wall paths: ghosts across every kind of link, corners, and bounce-back
+    into neighbours of every direction."""
+    rng = Rng(seed)
+    sigma = (1e-3, 1.3e-3, 1.1e-3)
+    mats = []
+    for m in range(n_materials):
+        while True:
+            t13, t23 = rng.uniform(45.0, 135.0), rng.uniform(45.0, 135.0)
+            if admissible(*sigma, theta13=t13, theta23=t23):
+                break
+        if moving and m % 2 == 1:
+            u = (U, 0.0) if (m // 2) % 2 == 0 else (0.0, -U)
+        else:
+            u = (0.0, 0.0)
+        mats.append(material(t13, t23, wall_u=u))
+    mask = np.zeros((ny, nx), dtype=np.uint8)
+    shapes = [[(0, 0)], [(0, 0), (1, 0), (0, 1), (1, 1)],
+              [(i, 0) for i in range(5)], [(0, j) for j in range(4)],
+              [(i, 0) for i in range(4)] + [(0, j) for j in range(1, 4)],
+              [(i, i) for i in range(4)]]
+    for _ in range(n_obstacles):
+        x0, y0 = rng.choice(nx), rng.choice(ny)
+        shape = shapes[rng.choice(len(shapes))]
+        mid = 1 + rng.choice(n_materials)
+        for dx, dy in shape:
+            mask[(y0 + dy) % ny, (x0 + dx) % nx] = mid
+    base = random_fields(nx, ny, seed=seed + 1000, amp=amp, geometry="periodic")
+    fl = dict(base["fluid"])
+    fl["sigma12"], fl["sigma13"], fl["sigma23"] = sigma
+    return _problem("obstacles_%dx%d_s%d" % (nx, ny, seed), nx, ny, fl, (1, 1), mask, mats,
+                    base["c1"], base["c2"], base["ux"], base["uy"], steps=0)
+
+
 def bandwidth_case(nx, ny):
     """Cylinder geometry without a drop (pure phase 3 at rest): the memory
     sweep workload."""
