@@ -619,6 +619,48 @@ def random_fields3(nx, ny, nz, seed=11, amp=0.2, geometry="channel", U=0.0,
                      periodic, mask, mats, c1, c2, u=(ux, uy, uz), gravity_z=gravity[2])
 
 
+def random_obstacles3(nx, ny, nz, seed=13, n_obstacles=30, n_materials=5, amp=0.2, U=0.01,
+                      moving=True):
+    """The 3-D counterpart of ``random_obstacles``: the smooth random mixture of
+    ``random_fields3`` in a fully periodic box scattered with small solids of
+    ``n_materials`` wetting materials (single voxels, 2x2x2 cubes, bars along
+    x, y and z, 3x3 plates, staircases along an x-z diagonal), anywhere, so
+    that they touch, wrap across the seams and cross tile and z-chunk
+    boundaries; with ``moving`` every other material moves at U along x or y
+    (walls move in the x-y plane)."""
+    rng = Rng(seed)
+    sigma = (1e-3, 1.3e-3, 1.1e-3)
+    mats = []
+    for m in range(n_materials):
+        while True:
+            t13, t23 = rng.uniform(45.0, 135.0), rng.uniform(45.0, 135.0)
+            if admissible(*sigma, theta13=t13, theta23=t23):
+                break
+        if moving and m % 2 == 1:
+            u = (U, 0.0) if (m // 2) % 2 == 0 else (0.0, -U)
+        else:
+            u = (0.0, 0.0)
+        mats.append(material(t13, t23, wall_u=u))
+    mask = np.zeros((nz, ny, nx), dtype=np.uint8)
+    shapes = [[(0, 0, 0)],
+              [(i, j, k) for i in range(2) for j in range(2) for k in range(2)],
+              [(i, 0, 0) for i in range(4)], [(0, j, 0) for j in range(4)],
+              [(0, 0, k) for k in range(4)],
+              [(i, j, 0) for i in range(3) for j in range(3)],
+              [(i, 0, i) for i in range(4)]]
+    for _ in range(n_obstacles):
+        x0, y0, z0 = rng.choice(nx), rng.choice(ny), rng.choice(nz)
+        shape = shapes[rng.choice(len(shapes))]
+        mid = 1 + rng.choice(n_materials)
+        for dx, dy, dz in shape:
+            mask[(z0 + dz) % nz, (y0 + dy) % ny, (x0 + dx) % nx] = mid
+    base = random_fields3(nx, ny, nz, seed=seed + 1000, amp=amp, geometry="periodic")
+    fl = dict(base["fluid"])
+    fl["sigma12"], fl["sigma13"], fl["sigma23"] = sigma
+    return _problem3("obstacles3_%dx%dx%d_s%d" % (nx, ny, nz, seed), nx, ny, nz, fl, (1, 1, 1),
+                     mask, mats, base["c1"], base["c2"], u=(base["ux"], base["uy"], base["uz"]))
+
+
 def large_lattice3(nx, ny, nz, seed=5):
     """Fully periodic three-phase D3Q19 lattice for size-limit tests: a
     smooth background mixture of all three phases (products of integer

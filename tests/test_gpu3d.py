@@ -65,6 +65,16 @@ def test_random_three_phase_3d(tlb, geometry, nx, ny, nz):
     _check(g, o)
 
 
+@pytest.mark.parametrize("nx,ny,nz", [(70, 18, 40), (40, 30, 26)])
+def test_scattered_obstacles_3d(tlb, nx, ny, nz):
+    """Scattered obstacles of five materials, half of them moving (every
+    obstacle shape of the generator, touching, wrapping, crossing tiles and
+    z-chunks): every field and population within 1e-12 after 100 steps."""
+    p = W.random_obstacles3(nx, ny, nz, seed=13, n_obstacles=40)
+    g, o = _pair(tlb, p, 100)
+    _check(g, o)
+
+
 def test_lambda_and_gravity_3d(tlb):
     p = W.random_fields3(48, 24, 20, geometry="sphere", rho=(10.0, 5.0, 1.0),
                          gravity=(1e-6, 0.0, -2e-6), lam=5e-2)
