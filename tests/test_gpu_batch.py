@@ -112,3 +112,35 @@ def test_batch_autotune_keeps_the_trajectory(tlb):
         ref.set_check_interval(0)
         ref.step(n)
         assert np.array_equal(s.read_populations(), ref.read_populations()), p["name"]
+
+
+def test_batch_with_optional_features_equals_oracle(tlb):
+    """One FP64 batch of a plain lattice with scattered obstacles, a channel with
+    a velocity boundary (Eqs. 51-53) and a lattice with lambda > 0 (Eqs. 5-6):
+    the launch runs the kernel variant with both optional parts for every
+    member, and each member must still equal the FP64 oracle within 1e-12 on
+    every field and population."""
+    import oracle
+    plain = W.random_obstacles(96, 70, seed=8, n_obstacles=25)
+    vel = W.random_fields(100, 37, geometry="channel", U=0.01, rho=(3.0, 2.0, 1.0), seed=9)
+    vel = dict(vel, mats=[vel["mats"][0], W.velocity_boundary((0.02, 0.0))], name=vel["name"] + "_v")
+    lam = W.random_fields(64, 40, geometry="cylinder", rho=(3.0, 2.0, 1.0), seed=10)
+    lam["fluid"] = dict(lam["fluid"], **{"lambda": 2e-2})
+    probs = [plain, vel, lam, W.reduction_case()]
+    steps = 201
+    members = [tlb.from_problem(p, "fp64") for p in probs]
+    b = tlb.Batch(8)
+    b.set(members)
+    b.step(steps)
+    b.sync()
+    for p, s in zip(probs, members):
+        o = oracle.Oracle(p)
+        o.init(p["c1"], p["c2"], p["ux"], p["uy"])
+        o.step(steps)
+        fg, fo = s.read_fields(), o.fields()
+        e = {k: float(np.abs(fg[k] - fo[k]).max()) for k in fo}
+        print("batch member %s: %s" % (p["name"], {k: "%.1e" % v for k, v in e.items()}), flush=True)
+        assert max(e.values()) <= 1e-12, (p["name"], e)
+        po = o.populations()
+        po[:, o.material != 0] = 0.0
+        assert np.abs(s.read_populations() - po).max() <= 1e-12, p["name"]
