@@ -231,6 +231,20 @@ tlb_status tlb_time_steps(tlb_ctx* ctx, int64_t nsteps, double* ms_per_step);
  * that does, or 16. */
 tlb_status tlb_set_tile_rows(tlb_ctx* ctx, int rows);
 
+/* Two steps per launch (a throughput knob; results are bitwise identical to
+ * stepping one at a time).  tlb_step and tlb_time_steps advance the lattice
+ * two steps per kernel launch whenever two or more steps remain before the
+ * next health check: one workgroup marches a strip of `rows` rows and 64
+ * columns through both steps (Eqs. 3-20, 42-45 applied twice), keeping the
+ * intermediate populations in on-chip memory, so the populations cross HBM
+ * once per two steps.  rows: a multiple of 4 in [8, 4096]; 0 turns it off
+ * (one step per launch); -1, the default, picks the tallest of 256, 128, 64
+ * rows that still gives each compute unit a strip (off for smaller
+ * lattices).  Applies to FP32 populations without velocity boundary nodes
+ * and with lambda = 0, on lattices whose nx is a multiple of 64; any other
+ * context steps one step per launch, and returns TLB_EINVAL for rows > 0. */
+tlb_status tlb_set_pair_rows(tlb_ctx* ctx, int rows);
+
 /* Picks the strip height with the shortest step among candidate values
  * (16 .. 128 rows, up to the lattice height) by timing steps_per_candidate
  * steps of each, and keeps it.  The timed steps are real steps of the solve

@@ -31,7 +31,7 @@ struct Layout {
     size_t pop_bytes;   // one lattice (27 planes)
     size_t rest_off;    // P16: offset of the two FP32 rest planes inside a lattice
     size_t hist_bytes;
-    size_t off_pop[2], off_hist, off_mat, off_mtab, off_desc, off_stage, off_part, off_result;
+    size_t off_pop[2], off_hist[2], off_mat, off_mtab, off_desc, off_stage, off_part, off_result;
     size_t stage_doubles;
     size_t total;
 };
@@ -52,7 +52,8 @@ Layout make_layout(int nx, int ny, int prec) {
     size_t o = 0;
     L.off_pop[0] = o; o += L.pop_bytes;
     L.off_pop[1] = o; o += L.pop_bytes;
-    L.off_hist = o; o += L.hist_bytes;
+    L.off_hist[0] = o; o += L.hist_bytes;   // history of the populations in off_pop[0]
+    L.off_hist[1] = o; o += L.hist_bytes;   // and of off_pop[1]
     L.off_mat = o; o += align_up(L.npad, kAlign);
     L.off_mtab = o; o += align_up(kMatStride * (kMaxMaterials + 1) * sizeof(double), kAlign);
     L.off_desc = o; o += kDescBytes;
@@ -84,6 +85,9 @@ struct tlb_ctx {
     int64_t check_interval = 100;
     int64_t since_check = 0;
     int cur = 0;  // lattice holding the current state
+    int pair_rows = -1;      // strip rows of the two-step kernel (0: one step per
+                             // launch; -1: pair_auto_rows when the kernel applies)
+    int pair_auto_rows = 0;  // default_pair_rows of this lattice
     int n_mats = 0;
     double mtab_host[kMatStride * (kMaxMaterials + 1)] = {};
     double* health = nullptr;  // pinned host copy of the last mass result
@@ -175,6 +179,17 @@ int default_rows(int nx, int ny, int prec, int cus) {
     return 16;
 }
 
+// Default strip height of the two-step kernel (one 11-wave workgroup per
+// CU): the tallest of 256, 128, 64 rows that still gives every CU a strip;
+// 0 (one step per launch) for a lattice too small for that.
+int default_pair_rows(int nx, int ny, int cus) {
+    const int tx = nx / kTileX;
+    static const int cand[] = {256, 128, 64};
+    for (int rows : cand)
+        if (tx * ((ny + rows - 1) / rows) >= cus) return rows;
+    return 0;
+}
+
 int device_cus() {
     int dev = 0, n = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -204,7 +219,8 @@ LatDesc<R, H> make_desc(tlb_ctx* c, const Consts<R>& k, int tile_begin, int cur)
     d.mtab = reinterpret_cast<const double*>(c->ws + c->L.off_mtab);
     d.buf[0] = popbuf(c, 0);
     d.buf[1] = popbuf(c, 1);
-    d.hist = reinterpret_cast<H*>(c->ws + c->L.off_hist);
+    d.hist[0] = reinterpret_cast<H*>(c->ws + c->L.off_hist[0]);
+    d.hist[1] = reinterpret_cast<H*>(c->ws + c->L.off_hist[1]);
     d.tile_begin = tile_begin;
     d.cur = cur;
     return d;
@@ -235,7 +251,7 @@ int ntiles(const tlb_ctx* c) { return c->grid.tiles_x * c->grid.tiles_y; }
 
 tlb_status run_mass(tlb_ctx* c, hipStream_t s) {
     hipError_t e = launch_mass(c->prec, c->grid, reinterpret_cast<uint8_t*>(c->ws + c->L.off_mat),
-                               c->ws + c->L.off_hist,
+                               c->ws + c->L.off_hist[c->cur],
                                reinterpret_cast<double*>(c->ws + c->L.off_part),
                                reinterpret_cast<double*>(c->ws + c->L.off_result), s);
     if (e != hipSuccess) return dev_fail(c, e, "mass reduction");
@@ -322,7 +338,9 @@ tlb_status tlb_create(int nx, int ny, tlb_precision p, const tlb_fluid* fl, void
     c->eta[1] = c->M[1] / (cs2 * (fl->tau2 - 0.5));
     fill_consts(c->c64, c);
     fill_consts(c->c32, c);
-    set_grid(c, default_rows(nx, ny, int(p), device_cus()));
+    const int cus = device_cus();
+    set_grid(c, default_rows(nx, ny, int(p), cus));
+    c->pair_auto_rows = default_pair_rows(nx, ny, cus);
     if (mass_scratch(&c->scratch) != hipSuccess) {
         delete c;
         return fail(nullptr, TLB_EDEVICE, "static scratch of tlb_mass_noalloc not found on this device");
@@ -455,7 +473,7 @@ tlb_status tlb_init_fields(tlb_ctx* c, const double* c1, const double* c2, const
     Grid g = c->grid;
     e = launch_init(c->prec, g, consts_ptr(c), reinterpret_cast<uint8_t*>(c->ws + c->L.off_mat),
                     reinterpret_cast<double*>(c->ws + c->L.off_mtab), stage, popbuf(c, 0),
-                    c->ws + c->L.off_hist, c->stream);
+                    c->ws + c->L.off_hist[0], c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return dev_fail(c, e, "init kernel");
     c->cur = 0;
@@ -472,14 +490,33 @@ static unsigned features(const tlb_ctx* c) {
     return (c->c64.nee != 0u ? 1u : 0u) | (c->fl.lambda != 0.0 ? 2u : 0u);
 }
 
+// The two-step kernel serves FP32 lattices without optional step parts whose
+// width is a multiple of 64 columns.
+static bool pair_ok(const tlb_ctx* c) {
+    return c->prec == P32 && features(c) == 0u && c->nx % kTileX == 0;
+}
+
 static tlb_status step_impl(tlb_ctx* c, int64_t nsteps, bool checks) {
-    for (int64_t s = 0; s < nsteps; ++s) {
-        hipError_t e = launch_step(c->prec, features(c), c->ws + c->L.off_desc, 1, ntiles(c),
-                                   c->cur, c->stream);
+    for (int64_t s = 0; s < nsteps;) {
+        // two steps in one launch when the kernel applies and no health check
+        // falls between them
+        const bool room = !checks || c->check_interval <= 0 ||
+                          c->check_interval - c->since_check >= 2;
+        const int pr = c->pair_rows < 0 ? c->pair_auto_rows : c->pair_rows;
+        const int n = (pr > 0 && pair_ok(c) && nsteps - s >= 2 && room) ? 2 : 1;
+        hipError_t e;
+        if (n == 2) {
+            const int tiles = c->grid.tiles_x * ((c->ny + pr - 1) / pr);
+            e = launch_step2(c->prec, c->ws + c->L.off_desc, tiles, c->cur, pr, c->stream);
+        } else {
+            e = launch_step(c->prec, features(c), c->ws + c->L.off_desc, 1, ntiles(c), c->cur,
+                            c->stream);
+        }
         if (e != hipSuccess) return dev_fail(c, e, "step kernel");
         c->cur = 1 - c->cur;
-        ++c->steps;
-        if (checks && c->check_interval > 0 && ++c->since_check >= c->check_interval) {
+        c->steps += n;
+        s += n;
+        if (checks && c->check_interval > 0 && (c->since_check += n) >= c->check_interval) {
             c->since_check = 0;
             if (!c->health) {
                 if (hipHostMalloc(reinterpret_cast<void**>(&c->health), 4 * sizeof(double)) !=
@@ -520,6 +557,21 @@ tlb_status tlb_set_tile_rows(tlb_ctx* c, int rows) {
         return fail(c, TLB_EINVAL, "strip rows must be a multiple of 4 in [8, 4096]");
     set_grid(c, rows);
     return c->inited ? upload_desc(c) : TLB_OK;
+}
+
+tlb_status tlb_set_pair_rows(tlb_ctx* c, int rows) {
+    if (!c) return fail(c, TLB_EINVAL, "null context");
+    if (rows == -1 || rows == 0) {
+        c->pair_rows = rows;
+        return TLB_OK;
+    }
+    if (rows < 8 || rows > 4096 || rows % 4)
+        return fail(c, TLB_EINVAL, "pair strip rows must be 0, -1 or a multiple of 4 in [8, 4096]");
+    if (!pair_ok(c))
+        return fail(c, TLB_EINVAL,
+                    "the two-step kernel needs FP32, no optional step parts and nx % 64 == 0");
+    c->pair_rows = rows;
+    return TLB_OK;
 }
 
 tlb_status tlb_read_fields(tlb_ctx* c, uint32_t mask, double* out) {
@@ -616,7 +668,7 @@ tlb_status tlb_mass_noalloc(tlb_ctx* c, double* dev_out) {
     if (!c->inited) return fail(c, TLB_ESTATE, "init_fields must precede mass");
     if (!c->scratch) return fail(c, TLB_EDEVICE, "static scratch not resolved");
     hipError_t e = launch_mass(c->prec, c->grid, reinterpret_cast<uint8_t*>(c->ws + c->L.off_mat),
-                               c->ws + c->L.off_hist, c->scratch, dev_out, c->stream);
+                               c->ws + c->L.off_hist[c->cur], c->scratch, dev_out, c->stream);
     if (e != hipSuccess) return dev_fail(c, e, "mass reduction");
     return TLB_OK;
 }
@@ -644,7 +696,7 @@ tlb_status tlb_checkpoint_save(tlb_ctx* c, void* buf) {
     hipError_t e = hipMemcpyAsync(b + 64, c->ws + c->L.off_pop[c->cur], c->L.pop_bytes,
                                   hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(b + 64 + c->L.pop_bytes, c->ws + c->L.off_hist, c->L.hist_bytes,
+        e = hipMemcpyAsync(b + 64 + c->L.pop_bytes, c->ws + c->L.off_hist[c->cur], c->L.hist_bytes,
                            hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return dev_fail(c, e, "checkpoint save");
@@ -664,7 +716,7 @@ tlb_status tlb_checkpoint_load(tlb_ctx* c, const void* buf) {
     hipError_t e = hipMemcpyAsync(c->ws + c->L.off_pop[0], b + 64, c->L.pop_bytes,
                                   hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(c->ws + c->L.off_hist, b + 64 + c->L.pop_bytes, c->L.hist_bytes,
+        e = hipMemcpyAsync(c->ws + c->L.off_hist[0], b + 64 + c->L.pop_bytes, c->L.hist_bytes,
                            hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return dev_fail(c, e, "checkpoint load");
@@ -957,6 +1009,14 @@ tlb_status tlb_autotune_rows(tlb_ctx* c, int steps_per_candidate, int* best_rows
     static const int cand[] = {16, 24, 32, 48, 64, 96, 128};
     int best = c->grid.tile_rows;
     double best_ms = 1e30;
+    // the candidates are strip heights of the one-step kernel: time it alone
+    const int pair_rows = c->pair_rows;
+    c->pair_rows = 0;
+    struct Restore {
+        tlb_ctx* c;
+        int rows;
+        ~Restore() { c->pair_rows = rows; }
+    } restore{c, pair_rows};
     const int limit = ((c->ny + 3) / 4) * 4;
     for (int rows : cand) {
         if (rows > (limit < 16 ? 16 : limit)) break;

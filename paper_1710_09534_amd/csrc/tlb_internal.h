@@ -64,7 +64,9 @@ struct Grid {
 
 // Device descriptor of one lattice for the step kernel (R: arithmetic type,
 // H: history storage type).  buf[cur] holds the current state at the step
-// the launch's parity 0 refers to.
+// the launch's parity 0 refers to; hist[b] holds the history planes that
+// belong to the populations of buf[b] (a step reads both from one index and
+// writes both to the other).
 template <typename R, typename H>
 struct LatDesc {
     Grid g;
@@ -72,7 +74,7 @@ struct LatDesc {
     const uint8_t* mat;
     const double* mtab;
     PopBuf buf[2];
-    H* hist;
+    H* hist[2];
     int tile_begin;   // prefix sum of the strip counts of the preceding lattices
     int cur;
 };
@@ -86,6 +88,12 @@ constexpr size_t kDescBytes = 512;  // >= sizeof(LatDesc), a multiple of 256
 // bit 1 some lattice has a bulk energy with lambda > 0.
 hipError_t launch_step(int prec, unsigned features, const void* descs, int ndesc,
                        int total_tiles, int parity, hipStream_t s);
+// Two steps of one lattice per launch (P32, a lattice without optional step
+// parts, nx a multiple of 64): descs holds its descriptor, total_tiles its
+// strip count at strips of `rows` rows (a multiple of 4); the result lands in
+// the buffer the first of two step_kernel launches would have written.
+hipError_t launch_step2(int prec, const void* descs, int total_tiles, int parity, int rows,
+                        hipStream_t s);
 // `consts` points to a host Consts<double> (P64) or Consts<float> (P32, P16);
 // `mtab` to the device material table.
 hipError_t launch_init(int prec, const Grid& g, const void* consts, const uint8_t* mat,

@@ -670,11 +670,10 @@ __device__ __forceinline__ void pull_f(const Grid& g, const Consts<typename Tr<P
 
 // Chemical potentials of one mu-ring node (mu column mcol, c column
 // mcol + 1) and its solid-neighbour mask.
-template <int P, unsigned F>
-__device__ __forceinline__ void ring_mu(Ring<P>& sm, const Consts<typename Tr<P>::R>& c,
-                                        int y, int y0, int mcol) {
+template <int P, unsigned F, class RG>
+__device__ __forceinline__ void ring_mu(RG& sm, const typename Tr<P>::R* mt,
+                                        const Consts<typename Tr<P>::R>& c, int y, int y0, int mcol) {
     using R = typename Tr<P>::R;
-    using RG = Ring<P>;
     const int sc[3] = {ring_slot(y - 1, y0), ring_slot(y, y0), ring_slot(y + 1, y0)};
     const int col = mcol + 1;
     const R* c1r[3];
@@ -728,8 +727,8 @@ __device__ __forceinline__ void ring_mu(Ring<P>& sm, const Consts<typename Tr<P>
         if (mask & kSelfBit) {
             mu1 = mu2 = mu3 = R(0);
         } else {
-            chem_pot<R, (F & kFeatVel) != 0, (F & kFeatLam) != 0>(c1r, c2r, mr, sm.mt, c, mu1,
-                                                                  mu2, mu3);
+            chem_pot<R, (F & kFeatVel) != 0, (F & kFeatLam) != 0>(c1r, c2r, mr, mt, c, mu1, mu2,
+                                                                  mu3);
         }
     }
     const int o = mu_slot(y, y0) * RG::MW + mcol;
@@ -739,33 +738,21 @@ __device__ __forceinline__ void ring_mu(Ring<P>& sm, const Consts<typename Tr<P>
     sm.nmask[o] = mask;
 }
 
-// Phase C of one node: time derivative (Eq. 19 in Eq. 11a), history,
-// equilibria (Eqs. 2, 4), sources (Eq. 11), BGK collision (Eq. 45), the 27
-// population stores at the node (or the spare row when `live` is false) and,
-// for a node next to solids, half-way bounce-back into the solid slots
-// (Eq. 44) with the moving-wall term -2 w_k a e_k.u_w / c_s^2 (a = c_i for
-// f^i, rho for g).
-template <int P, unsigned F>
-__device__ __forceinline__ void node_update(const Grid& g, const Consts<typename Tr<P>::R>& c,
-                                            const Stencil<typename Tr<P>::R>& s,
-                                            const typename Tr<P>::R* mt, const Nb32& nb,
-                                            unsigned idx, bool live, unsigned mask,
-                                            typename Tr<P>::R* f1, typename Tr<P>::R* f2,
-                                            const typename Tr<P>::R* gg,
-                                            const typename Tr<P>::R* ho, const LatView<P>& dst,
-                                            rsrc_t hist, unsigned hstride) {
+// Where phase C puts a node's results in HBM: the node's own slots (byte
+// offsets ob of an S element and o4 of a 4-byte element, both kDiscard for a
+// lane without a fluid output node), slots of its neighbours, and the history
+// planes.
+template <int P>
+struct HbmSink {
     using R = typename Tr<P>::R;
     using HT = typename Tr<P>::H;
-    constexpr bool VEL = (F & kFeatVel) != 0;
-    const NodeMacro<R> o = node_macro<R, true, VEL>(s, c, gg, mask);
-    const R d1x = o.c1 * o.ux - ho[0] * ho[2], d1y = o.c1 * o.uy - ho[0] * ho[3];
-    const R d2x = o.c2 * o.ux - ho[1] * ho[2], d2y = o.c2 * o.uy - ho[1] * ho[3];
-    // byte offsets of this node's slots, or kDiscard for a lane without a
-    // fluid output node
-    const unsigned ob = live ? idx * unsigned(sizeof(typename Tr<P>::S)) : kDiscard;
-    const unsigned o4 = live ? idx * 4u : kDiscard;
-    {
-        const HT hv[4] = {HT(o.c1), HT(o.c2), HT(o.ux), HT(o.uy)};
+    const LatView<P>& dst;
+    const Consts<R>& c;
+    rsrc_t hist;
+    unsigned hstride;
+    Nb32 nb;
+    unsigned ob, o4;
+    __device__ __forceinline__ void history(const HT (&hv)[4]) const {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             if constexpr (P == P64)
@@ -777,6 +764,44 @@ __device__ __forceinline__ void node_update(const Grid& g, const Consts<typename
                 __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, hv[q]), hist,
                                                       int(o4), int(q * hstride), 0);
         }
+    }
+    // populations k of f^1, f^2 and g of the node
+    __device__ __forceinline__ void own(int k, R x1, R x2, R gv) const {
+        bst12<P>(dst, c, k, ob, o4, x1, x2);
+        bst<P>(dst, c, 2, k, ob, o4, gv);
+    }
+    // populations q of the neighbour x + e_k
+    __device__ __forceinline__ void link(int k, int q, R x1, R x2, R gv) const {
+        const unsigned sn = nb.dn(k);
+        const unsigned sb = sn * unsigned(sizeof(typename Tr<P>::S)), s4 = sn * 4u;
+        bst12<P>(dst, c, q, sb, s4, x1, x2);
+        bst<P>(dst, c, 2, q, sb, s4, gv);
+    }
+};
+
+// Phase C of one node: time derivative (Eq. 19 in Eq. 11a), history,
+// equilibria (Eqs. 2, 4), sources (Eq. 11), BGK collision (Eq. 45), the 27
+// post-collision populations of the node (or nothing when `live` is false)
+// and, for a node next to solids, half-way bounce-back into the solid slots
+// (Eq. 44) with the moving-wall term -2 w_k a e_k.u_w / c_s^2 (a = c_i for
+// f^i, rho for g); `out` stores them (HbmSink, or the LDS ring of the
+// two-level march).
+template <int P, unsigned F, class Sink>
+__device__ __forceinline__ void node_update(const Consts<typename Tr<P>::R>& c,
+                                            const Stencil<typename Tr<P>::R>& s,
+                                            const typename Tr<P>::R* mt, bool live, unsigned mask,
+                                            typename Tr<P>::R* f1, typename Tr<P>::R* f2,
+                                            const typename Tr<P>::R* gg,
+                                            const typename Tr<P>::R* ho, const Sink& out) {
+    using R = typename Tr<P>::R;
+    using HT = typename Tr<P>::H;
+    constexpr bool VEL = (F & kFeatVel) != 0;
+    const NodeMacro<R> o = node_macro<R, true, VEL>(s, c, gg, mask);
+    const R d1x = o.c1 * o.ux - ho[0] * ho[2], d1y = o.c1 * o.uy - ho[0] * ho[3];
+    const R d2x = o.c2 * o.ux - ho[1] * ho[2], d2y = o.c2 * o.uy - ho[1] * ho[3];
+    {
+        const HT hv[4] = {HT(o.c1), HT(o.c2), HT(o.ux), HT(o.uy)};
+        out.history(hv);
     }
     // The collision of Eq. 45 with the equilibria of Eqs. 2 and 4 and the
     // sources of Eq. 11, regrouped into per-node scalars and vectors so that
@@ -825,8 +850,6 @@ __device__ __forceinline__ void node_update(const Grid& g, const Consts<typename
             if (!(mask & (1u << (kVelShift + kn)))) continue;
             const int mn = s.m[EY[kn] + 1][0];
             const R uwx = mt[kMatStride * mn + 3], uwy = mt[kMatStride * mn + 4];
-            const unsigned sn = nb.dn(kn);
-            const unsigned sb = sn * unsigned(sizeof(typename Tr<P>::S)), s4 = sn * 4u;
             // e_k.V_i at u_w is 3 e_k.u_w a_i with a_i = c_i / tau_i + (1 - 1/(2 tau_i))
             // (c_i - c_i^old); e_k.G1 = 3 fsg e_k.F + 3 am e_k.u_w, G0 = 3 fsg u_w.F
             const R a1 = S1 * (c.itau1 * o.c1 + c.fs1 * (o.c1 - ho[0]));
@@ -849,8 +872,7 @@ __device__ __forceinline__ void node_update(const Grid& g, const Consts<typename
                 const R gu = omg * (gg[k] + o.rho * (skw - sku)) +
                              w * (Pg + R(3) * (fsg * (eF - wF) + o.am * ew)) +
                              skw * (Rg + fsg * (eA - wA));
-                bst12<P>(dst, c, k, sb, s4, f1u, f2u);
-                bst<P>(dst, c, 2, k, sb, s4, gu);
+                out.link(kn, k, f1u, f2u, gu);
             }
         }
     }
@@ -873,8 +895,7 @@ __device__ __forceinline__ void node_update(const Grid& g, const Consts<typename
             f2[k] = om2 * f2[k] + w * (P2 + eV2);
             g2[k] = omg * gg[k] + w * (Pg + eG - G0) + sk * (Rg + fsg * (eA - uA));
         }
-        bst12<P>(dst, c, k, ob, o4, f1[k], f2[k]);
-        bst<P>(dst, c, 2, k, ob, o4, g2[k]);
+        out.own(k, f1[k], f2[k], g2[k]);
     }
     if (live && (mask & kWallBits)) {
 #pragma unroll
@@ -883,10 +904,7 @@ __device__ __forceinline__ void node_update(const Grid& g, const Consts<typename
                 const int mn = s.m[EY[k] + 1][EX[k]];
                 const R* tm = &mt[kMatStride * mn];
                 const R corr = -R(6) * wgt<R>(k) * (R(EX[k]) * tm[3] + R(EY[k]) * tm[4]);
-                const unsigned sn = nb.dn(k);
-                const unsigned sb = sn * unsigned(sizeof(typename Tr<P>::S)), s4 = sn * 4u;
-                bst12<P>(dst, c, OPP[k], sb, s4, f1[k] + corr * sc1, f2[k] + corr * sc2);
-                bst<P>(dst, c, 2, OPP[k], sb, s4, g2[k] + corr * o.rho);
+                out.link(k, OPP[k], f1[k] + corr * sc1, f2[k] + corr * sc2, g2[k] + corr * o.rho);
             }
         }
     }
@@ -898,8 +916,9 @@ template <int P, unsigned F>
 __device__ __forceinline__ void step_tile(const Grid& g, const Consts<typename Tr<P>::R>& c,
                                           const uint8_t* __restrict__ mat,
                                           const double* __restrict__ mtab, PopBuf srcb,
-                                          PopBuf dstb, typename Tr<P>::H* __restrict__ histp,
-                                          int t, Ring<P>& sm) {
+                                          PopBuf dstb, const typename Tr<P>::H* __restrict__ histi,
+                                          typename Tr<P>::H* __restrict__ histo, int t,
+                                          Ring<P>& sm) {
     using R = typename Tr<P>::R;
     using HT = typename Tr<P>::H;
     using RG = Ring<P>;
@@ -927,7 +946,7 @@ __device__ __forceinline__ void step_tile(const Grid& g, const Consts<typename T
             const int r = threadIdx.x / RG::MW;
             const int mcol = threadIdx.x - r * RG::MW;
             const int y = Y + 1 + r;
-            if (y >= y0 - 1) ring_mu<P, F>(sm, c, y, y0, mcol);  // prologue: rows below y0-1 lack neighbours
+            if (y >= y0 - 1) ring_mu<P, F>(sm, sm.mt, c, y, y0, mcol);  // prologue: rows below y0-1 lack neighbours
         }
     };
 
@@ -974,7 +993,8 @@ __device__ __forceinline__ void step_tile(const Grid& g, const Consts<typename T
     const bool out_lane = x0 + lane < g.nx;
     const LatView<P> dst = lat_view<P>(dstb, g.npad);
     const unsigned hstride = unsigned(g.npad * long(sizeof(HT)));
-    const rsrc_t hist = make_rsrc(histp, 4u * hstride);
+    const rsrc_t hist = make_rsrc(histi, 4u * hstride);      // history read (Eq. 19)
+    const rsrc_t hist_out = make_rsrc(histo, 4u * hstride);  // and written
     if constexpr (P == P64) {
         // Two register sets of pulled populations alternate (the loop is
         // unrolled by two): phase A of iteration it consumes the set pulled
@@ -1075,7 +1095,10 @@ __device__ __forceinline__ void step_tile(const Grid& g, const Consts<typename T
                           fm);
                 __builtin_amdgcn_sched_barrier(0);
             }
-            node_update<P, F>(g, c, s, sm.mt, nb, idx, live, mask, u1, u2, gg, ho, dst, hist, hstride);
+            const HbmSink<P> out{dst, c, hist_out, hstride, nb,
+                                 live ? idx * unsigned(sizeof(typename Tr<P>::S)) : kDiscard,
+                                 live ? idx * 4u : kDiscard};
+            node_update<P, F>(c, s, sm.mt, live, mask, u1, u2, gg, ho, out);
         };
 
         pull_f<P>(g, c, src, matr, gxl, wrapc(y0 - 2 + w, g.ny), true, nf1, nf2, nm);
@@ -1197,8 +1220,10 @@ __device__ __forceinline__ void step_tile(const Grid& g, const Consts<typename T
                               nf2, nm);
                     __builtin_amdgcn_sched_barrier(0);
                 }
-                node_update<P, F>(g, c, s, sm.mt, nb, idx, live, mask, cf1, cf2, gg, ho, dst, hist,
-                                  hstride);
+                const HbmSink<P> out{dst, c, hist_out, hstride, nb,
+                                     live ? idx * unsigned(sizeof(typename Tr<P>::S)) : kDiscard,
+                                     live ? idx * 4u : kDiscard};
+                node_update<P, F>(c, s, sm.mt, live, mask, cf1, cf2, gg, ho, out);
             }
             // phase A of the next iteration (after the last one its loads are
             // all out of range)
@@ -1237,7 +1262,490 @@ void step_kernel(const unsigned char* __restrict__ descs, int ndesc, int total_t
     const Grid g = d.g;
     const Consts<typename Tr<P>::R> c = d.c;
     const int sb = (d.cur + parity) & 1;
-    step_tile<P, F>(g, c, d.mat, d.mtab, d.buf[sb], d.buf[sb ^ 1], d.hist, L - d.tile_begin, sm);
+    step_tile<P, F>(g, c, d.mat, d.mtab, d.buf[sb], d.buf[sb ^ 1], d.hist[sb], d.hist[sb ^ 1],
+                    L - d.tile_begin, sm);
+}
+
+// ------------------------------------------------------------ two-step march
+// step2_kernel advances a lattice by two time steps in one pass over its
+// populations (FP32 storage, no optional parts).  A workgroup of eleven
+// waves marches a 64-column strip of rows [y0, y0 + H) at two time levels:
+//   level 1 collides rows [y0-4, y0+H+4) and columns [x0-3, x0+67) from the
+//     populations in HBM (the same phases as step_kernel) and keeps its
+//     post-collision populations in an LDS ring of 8 rows (27 planes x 70
+//     columns) instead of storing them;
+//   level 2 trails level 1 by 8 rows, pulls from that ring, collides rows
+//     [y0, y0+H) of columns [x0, x0+64) and stores to HBM.
+// Level 2 is step_kernel's second step exactly: every node goes through the
+// same pulls, moments, chemical potentials and collision (the same device
+// functions), so two launches of step_kernel and one of step2_kernel give the
+// same numbers.  Level 1 needs its own radius-3 frame (a node's c needs pulls
+// from x +- 1, its mu the c of x +- 1, its collision the mu of x +- 1), hence
+// 6 extra columns of collisions and 10 of c per 64 columns.
+// Waves: 0-3 level-1 rows, 4 level-1 c on the 10 side columns, 5 level-1
+// collisions on the 6 side columns, 6-9 level-2 rows, 10 level-2 c on the 4
+// side columns.  Per iteration (four rows of each level) three barriers split
+//   slot 1: level-1 mu (waves 0-4) | level-2 mu (waves 6-10);
+//   slot 2: level-1 collisions into the ring (waves 0-3, 5) | level-2
+//           collisions to HBM (waves 6-9), so that the nine colliding waves
+//           share the SIMDs at once;
+//   slot 3: level-1 c of the next rows and their g / history loads (waves
+//           0-5) | level-2 c of the next rows from the ring (waves 6-10).
+// Level 2 reads ring rows only after the barrier that follows their level-1
+// collision, and a ring slot is rewritten only after its last reader (see
+// the row arithmetic at step2_tile).  With two slots (level-2 collision and
+// c in one, level-1 collision in the other) the levels' collisions ran one
+// after the other: 98.6 against 85.8 us per step on a 1024 x 2048 lattice.
+// History planes: level 1 reads the
+// history of the launch's input state and passes its own (c, u) to level 2
+// through an LDS ring; level 2 writes the output history to the other
+// history buffer (another strip's level 1 may still read the input one).
+constexpr int kStep2Waves = 11;
+constexpr int kStep2Threads = kStep2Waves * kTileX;
+
+template <int P>
+struct Ring2 {
+    using R = typename Tr<P>::R;
+    static constexpr int PW = kTileX + 6;   // population ring columns x0-3 .. x0+66
+    static constexpr int PS = PW + 1;       // row stride: column PW takes discarded stores
+    static constexpr int PR = 8;            // population / history ring rows
+    // c and mu rings of one level: c on columns x0-HC .. x0+63+HC, mu on one
+    // column fewer each side (the layout ring_mu expects)
+    template <int HC>
+    struct Lvl {
+        static constexpr int W = kTileX + 2 * HC, MW = kTileX + 2 * HC - 2;
+        R c1[16 * W];
+        R c2[16 * W];
+        R mu1[8 * MW];
+        R mu2[8 * MW];
+        R mu3[8 * MW];
+        uint32_t nmask[8 * MW];
+        uint8_t m[16 * W];
+    };
+    R pop[27][PR][PS];                       // level-1 post-collision populations
+    R stash1[2][2][18][kTileX];              // level-1 waves 2, 3 (as in Ring)
+    R stash2[2][2][27][kTileX];              // level-2 waves 2, 3
+    R hist[PR + 1][4][kTileX];               // level-1 (c1, c2, ux, uy) for level 2; row PR
+                                             // takes discarded stores
+    R mt[kMatStride * (kMaxMaterials + 1)];
+    Lvl<5> a;                                // level 1
+    Lvl<2> b;                                // level 2
+};
+
+// ring row of a population / history row y of a strip whose level 1 starts
+// at row yb1 (rows yb1-1 .. are written)
+__device__ __forceinline__ int pop_slot(int y, int yb1) { return (y - yb1 + 8) & 7; }
+
+// Level-1 destination of a node's results: its column `col` (PW when the
+// node is not live: the discard column) and row slot `rs` of the population
+// ring, bounce-back into the ring's neighbour slots (to the discard column
+// outside the ring's columns: no level-2 node pulls them), and its history
+// (`hist`: its slot in the history ring, or in the discard row).  No store
+// is behind a branch, so node_update compiles to the same arithmetic as with
+// HbmSink.
+template <int P>
+struct LdsSink {
+    using R = typename Tr<P>::R;
+    using HT = typename Tr<P>::H;
+    using RG = Ring2<P>;
+    R* pop;
+    R* hist;
+    int rs, col;
+    __device__ __forceinline__ void history(const HT (&hv)[4]) const {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) hist[q * kTileX] = hv[q];
+    }
+    __device__ __forceinline__ void own(int k, R x1, R x2, R gv) const {
+        pop[(k * RG::PR + rs) * RG::PS + col] = x1;
+        pop[((9 + k) * RG::PR + rs) * RG::PS + col] = x2;
+        pop[((18 + k) * RG::PR + rs) * RG::PS + col] = gv;
+    }
+    __device__ __forceinline__ void link(int k, int q, R x1, R x2, R gv) const {
+        const int r = (rs + EY[k]) & (RG::PR - 1);
+        const int c0 = col + EX[k];
+        const int cc = unsigned(c0) < unsigned(RG::PW) ? c0 : RG::PW;
+        pop[(q * RG::PR + r) * RG::PS + cc] = x1;
+        pop[((9 + q) * RG::PR + r) * RG::PS + cc] = x2;
+        pop[((18 + q) * RG::PR + r) * RG::PS + cc] = gv;
+    }
+};
+
+// One strip of one lattice, two steps.  Rows: level 1 is step_tile's march
+// with base yb1 = y0 - 4 and rows + 8 rows (iterations it = -1 .. nit2 + 1,
+// Y1 = yb1 + 4 it); level 2 is the same march with base y0 (iterations
+// j = -1 .. nit2 - 1, Y2 = y0 + 4 j).  At loop index it: slot 1 level-1 mu
+// of it and level-2 mu of j = it - 3; slot 2 the collisions of level 1 (it)
+// and level 2 (j = it - 3, Y2 = Y1 - 8); slot 3 level-1 c of it + 1 and
+// level-2 c of j = it - 2.  Level-2 c of j = it - 2 pulls ring rows
+// Y2+1 .. Y2+6 = Y1-3 .. Y1+2, collided by level 1 in slot 2 of this or an
+// earlier index (rows <= Y1 + 3; later collisions write no row below Y1 + 3,
+// their bounce-back included).
+// Level-1 collision it writes rows Y1-1 .. Y1+4, whose slots (mod 8) held
+// rows Y1-9 .. Y1-4, last read in slot 3 of index it - 1; the rows read in
+// slot 3 of index it (Y1-3 .. Y1+2) are not among them.  The history ring
+// row of a level-2 collision row is read with that row's c (slot 3, one
+// index before the collision), before level 1 rewrites it in slot 2.
+template <int P>
+__device__ __forceinline__ void step2_tile(const Grid& g, int H, const Consts<typename Tr<P>::R>& c,
+                                           const uint8_t* __restrict__ mat,
+                                           const double* __restrict__ mtab, PopBuf srcb,
+                                           PopBuf dstb, const typename Tr<P>::H* __restrict__ histi,
+                                           typename Tr<P>::H* __restrict__ histo, int t,
+                                           Ring2<P>& sm) {
+    static_assert(P == P32, "the two-step march keeps FP32 populations in LDS");
+    using R = typename Tr<P>::R;
+    using HT = typename Tr<P>::H;
+    using RG = Ring2<P>;
+    using LA = typename RG::template Lvl<5>;
+    using LB = typename RG::template Lvl<2>;
+    const int x0 = (t % g.tiles_x) * kTileX;
+    const int y0 = (t / g.tiles_x) * H;
+    const int rows = g.ny - y0 < H ? g.ny - y0 : H;
+    const int nit2 = (rows + 3) / 4;
+    const int yb1 = y0 - 4, rows1 = rows + 8;
+    const int nit1 = nit2 + 2;
+    const int ylast1 = yb1 + rows1 + 1;                    // last level-1 row whose c is needed
+    const int lane = threadIdx.x & (kTileX - 1);
+    const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kTileX);  // wave-uniform
+    const LatView<P> src = lat_view<P>(srcb, g.npad);
+    const rsrc_t matr = make_rsrc(mat, unsigned(g.npad));
+    const auto* gmtab = (const __attribute__((address_space(1))) double*)mtab;
+    for (int i = threadIdx.x; i < kMatStride * (kMaxMaterials + 1); i += kStep2Threads)
+        sm.mt[i] = R(gmtab[i]);
+    const unsigned hstride = unsigned(g.npad * long(sizeof(HT)));
+    const rsrc_t hist_in = make_rsrc(histi, 4u * hstride);
+    const int itmax = nit2 + 2;
+
+    // level-1 mu of iteration it (rows Y1+1 .. Y1+4, mu columns 0..71):
+    // threads 0..287; level-2 mu of iteration j (rows Y2+1 .. Y2+4, columns
+    // 0..65): threads 384..647
+    auto b1 = [&](int it) {
+        if (threadIdx.x < 4 * LA::MW) {
+            const int r = threadIdx.x / LA::MW;
+            const int mcol = threadIdx.x - r * LA::MW;
+            const int y = yb1 + 4 * it + 1 + r;
+            if (y >= yb1 - 1) ring_mu<P, 0>(sm.a, sm.mt, c, y, yb1, mcol);
+        }
+    };
+    auto b2 = [&](int j) {
+        const int tt = int(threadIdx.x) - 6 * kTileX;
+        if (tt >= 0 && tt < 4 * LB::MW) {
+            const int r = tt / LB::MW;
+            const int mcol = tt - r * LB::MW;
+            const int y = y0 + 4 * j + 1 + r;
+            if (y >= y0 - 1) ring_mu<P, 0>(sm.b, sm.mt, c, y, y0, mcol);
+        }
+    };
+
+    if (w < 6) {
+        // ================================ level 1 (HBM -> ring)
+        R nf1[9], nf2[9];
+        uint8_t nm;
+        if (w == 4) {
+            // c of the 10 side columns x0-5 .. x0-1, x0+64 .. x0+68 (c ring
+            // columns 0..4, 69..73), lane = column + 10 * (row - Y1 - 2)
+            const int hc = lane % 10;
+            const int hr = lane / 10;
+            const bool act = lane < 40;
+            const int ccol = hc < 5 ? hc : kTileX + hc;
+            const int gx = wrapc(x0 - 5 + ccol, g.nx);
+            auto halo_a = [&](int it) {
+                const int Y = yb1 + 4 * it;
+                const R a = sum_pop<P>(c, 0, nf1), b = sum_pop<P>(c, 1, nf2);
+                if (act) {
+                    const int sl = ring_slot(Y + 2 + hr, yb1) * LA::W + ccol;
+                    const bool fl = nm == 0;
+                    sm.a.c1[sl] = fl ? a : R(0);
+                    sm.a.c2[sl] = fl ? b : R(0);
+                    sm.a.m[sl] = nm;
+                }
+                pull_f<P>(g, c, src, matr, gx, wrapc(Y + 6 + hr, g.ny), act && Y + 6 + hr <= ylast1,
+                          nf1, nf2, nm);
+            };
+            pull_f<P>(g, c, src, matr, gx, wrapc(yb1 - 2 + hr, g.ny), act, nf1, nf2, nm);
+            halo_a(-1);
+            for (int it = -1; it <= itmax; ++it) {
+                __syncthreads();
+                if (it <= nit1 - 1) b1(it);
+                __syncthreads();
+                __syncthreads();
+                if (it + 1 <= nit1 - 1) halo_a(it + 1);
+            }
+            return;
+        }
+        if (w == 5) {
+            // collisions of the 6 side columns x0-3 .. x0-1, x0+64 .. x0+66
+            // (ring columns 0..2, 67..69), lane = column + 6 * (row - Y1);
+            // their pulls, g and history are loaded one slot ahead
+            const int hc = lane % 6;
+            const int hr = lane / 6;
+            const bool act = lane < 24;
+            const int pcol = hc < 3 ? hc : kTileX + hc;
+            const int gx = wrapc(x0 - 3 + pcol, g.nx);
+            R gg[9], ho[4];
+            Nb32 nb;
+            auto side_a = [&](int it) {
+                const int yo = yb1 + 4 * it + hr;
+                const bool on = act && yo < yb1 + rows1;
+                pull_f<P>(g, c, src, matr, gx, wrapc(yo, g.ny), on, nf1, nf2, nm);
+                nb = make_nb32(g, gx, wrapc(yo, g.ny));
+                const unsigned idx = nb.r0 + nb.x0;
+#pragma unroll
+                for (int k = 0; k < 9; ++k) gg[k] = bld<P>(src, c, 2, k, nb.up(k), on);
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    ho[q] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                        hist_in, int(on ? idx * 4u : kDiscard), int(q * hstride), 0));
+            };
+            auto side_c = [&](int it) {
+                const int yo = yb1 + 4 * it + hr;
+                Stencil<R> s;
+                const int sl[3] = {ring_slot(yo - 1, yb1), ring_slot(yo, yb1), ring_slot(yo + 1, yb1)};
+                const int ml[3] = {mu_slot(yo - 1, yb1), mu_slot(yo, yb1), mu_slot(yo + 1, yb1)};
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    s.c1[r] = &sm.a.c1[sl[r] * LA::W + pcol + 2];
+                    s.c2[r] = &sm.a.c2[sl[r] * LA::W + pcol + 2];
+                    s.m[r] = &sm.a.m[sl[r] * LA::W + pcol + 2];
+                    s.mu1[r] = &sm.a.mu1[ml[r] * LA::MW + pcol + 1];
+                    s.mu2[r] = &sm.a.mu2[ml[r] * LA::MW + pcol + 1];
+                }
+                s.mu3 = sm.a.mu3[ml[1] * LA::MW + pcol + 1];
+                const unsigned mask = act ? sm.a.nmask[ml[1] * LA::MW + pcol + 1] : kSelfBit;
+                const bool live = act && yo < yb1 + rows1 && !(mask & kSelfBit);
+                const LdsSink<P> out{&sm.pop[0][0][0], &sm.hist[RG::PR][0][lane], pop_slot(yo, yb1),
+                                     live ? pcol : RG::PW};
+                node_update<P, 0>(c, s, sm.mt, live, mask, nf1, nf2, gg, ho, out);
+            };
+            for (int it = -1; it <= itmax; ++it) {
+                __syncthreads();
+                if (it <= nit1 - 1) b1(it);
+                __syncthreads();
+                if (it >= 0 && it <= nit1 - 1) side_c(it);
+                __syncthreads();
+                if (it + 1 <= nit1 - 1) side_a(it + 1);
+            }
+            return;
+        }
+
+        // ---- level-1 row waves: columns x0 .. x0+63 (c ring column lane+5,
+        //      mu column lane+4, population ring column lane+3)
+        const int gxl = x0 + lane;
+        R cf1[9], cf2[9], gg[9], ho[4];
+        int yo = 0;
+        auto phase_a = [&](int it) {
+            const int Y = yb1 + 4 * it;
+            const int sl = ring_slot(Y + 2 + w, yb1) * LA::W + lane + 5;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                cf1[k] = nf1[k];
+                cf2[k] = nf2[k];
+            }
+            const R a = sum_pop<P>(c, 0, cf1), b = sum_pop<P>(c, 1, cf2);
+            const bool fl = nm == 0;
+            sm.a.c1[sl] = fl ? a : R(0);
+            sm.a.c2[sl] = fl ? b : R(0);
+            sm.a.m[sl] = nm;
+            if (w >= 2) {
+#pragma unroll
+                for (int k = 0; k < 9; ++k) {
+                    sm.stash1[it & 1][w - 2][k][lane] = cf1[k];
+                    sm.stash1[it & 1][w - 2][9 + k][lane] = cf2[k];
+                }
+            }
+            yo = Y + ((w + 2) & 3);
+            const Nb32 nb = make_nb32(g, gxl, wrapc(yo, g.ny));
+            const unsigned idx = nb.r0 + nb.x0;
+            const bool gon = yo >= yb1 && yo < yb1 + rows1;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) gg[k] = bld<P>(src, c, 2, k, nb.up(k), gon);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                ho[q] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                    hist_in, int(gon ? idx * 4u : kDiscard), int(q * hstride), 0));
+            __builtin_amdgcn_sched_barrier(0);
+            if (it < 0)
+                pull_f<P>(g, c, src, matr, gxl, wrapc(Y + 6 + w, g.ny), Y + 6 + w <= ylast1, nf1,
+                          nf2, nm);
+            __builtin_amdgcn_sched_barrier(0);
+        };
+        auto phase_c = [&](int it) {
+            Stencil<R> s;
+            const int sl[3] = {ring_slot(yo - 1, yb1), ring_slot(yo, yb1), ring_slot(yo + 1, yb1)};
+            const int ml[3] = {mu_slot(yo - 1, yb1), mu_slot(yo, yb1), mu_slot(yo + 1, yb1)};
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                s.c1[r] = &sm.a.c1[sl[r] * LA::W + lane + 5];
+                s.c2[r] = &sm.a.c2[sl[r] * LA::W + lane + 5];
+                s.m[r] = &sm.a.m[sl[r] * LA::W + lane + 5];
+                s.mu1[r] = &sm.a.mu1[ml[r] * LA::MW + lane + 4];
+                s.mu2[r] = &sm.a.mu2[ml[r] * LA::MW + lane + 4];
+            }
+            s.mu3 = sm.a.mu3[ml[1] * LA::MW + lane + 4];
+            const unsigned mask = sm.a.nmask[ml[1] * LA::MW + lane + 4];
+            const bool live = yo < yb1 + rows1 && !(mask & kSelfBit);
+            if (w >= 2) {
+#pragma unroll
+                for (int k = 0; k < 9; ++k) {
+                    cf1[k] = sm.stash1[(it - 1) & 1][w - 2][k][lane];
+                    cf2[k] = sm.stash1[(it - 1) & 1][w - 2][9 + k][lane];
+                }
+            }
+            {
+                const int Y = yb1 + 4 * it;
+                __builtin_amdgcn_sched_barrier(0);
+                pull_f<P>(g, c, src, matr, gxl, wrapc(Y + 6 + w, g.ny), Y + 6 + w <= ylast1, nf1,
+                          nf2, nm);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            const int ps = pop_slot(yo, yb1);
+            const LdsSink<P> out{&sm.pop[0][0][0], &sm.hist[live ? ps : RG::PR][0][lane], ps,
+                                 live ? lane + 3 : RG::PW};
+            node_update<P, 0>(c, s, sm.mt, live, mask, cf1, cf2, gg, ho, out);
+        };
+        pull_f<P>(g, c, src, matr, gxl, wrapc(yb1 - 2 + w, g.ny), true, nf1, nf2, nm);
+        phase_a(-1);
+        for (int it = -1; it <= itmax; ++it) {
+            __syncthreads();
+            if (it <= nit1 - 1) b1(it);
+            __syncthreads();
+            if (it >= 0 && it <= nit1 - 1) phase_c(it);
+            __syncthreads();
+            if (it + 1 <= nit1 - 1) phase_a(it + 1);
+        }
+        return;
+    }
+
+    // ==================================== level 2 (ring -> HBM)
+    const LatView<P> dst = lat_view<P>(dstb, g.npad);
+    const rsrc_t hist_out = make_rsrc(histo, 4u * hstride);
+    // pull of the 18 (or, with g, 27) populations of node (column pc of the
+    // population ring + 0, row y) from the ring: plane q of x - e_k
+    auto ring_pull = [&](int pc, int y, R* f1, R* f2, R* gv) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const int r = pop_slot(y - EY[k], yb1);
+            const int cc = pc - EX[k];
+            f1[k] = sm.pop[k][r][cc];
+            f2[k] = sm.pop[9 + k][r][cc];
+            if (gv) gv[k] = sm.pop[18 + k][r][cc];
+        }
+    };
+    if (w == 10) {
+        // c of the 4 side columns x0-2, x0-1, x0+64, x0+65 (c ring columns
+        // 0, 1, 66, 67), lane = column + 4 * (row - Y2 - 2)
+        const int hc = lane & 3;
+        const int hr = (lane >> 2) & 3;
+        const bool act = lane < 16;
+        const int ccol = hc < 2 ? hc : kTileX + hc;
+        auto halo_a2 = [&](int j) {
+            const int y = y0 + 4 * j + 2 + hr;
+            R f1[9], f2[9];
+            ring_pull(ccol + 1, y, f1, f2, nullptr);
+            const uint8_t m = sm.a.m[ring_slot(y, yb1) * LA::W + ccol + 3];
+            const R a = sum_pop<P>(c, 0, f1), b = sum_pop<P>(c, 1, f2);
+            if (act) {
+                const int sl = ring_slot(y, y0) * LB::W + ccol;
+                const bool fl = m == 0;
+                sm.b.c1[sl] = fl ? a : R(0);
+                sm.b.c2[sl] = fl ? b : R(0);
+                sm.b.m[sl] = m;
+            }
+        };
+        for (int it = -1; it <= itmax; ++it) {
+            __syncthreads();
+            if (it - 3 >= -1 && it - 3 <= nit2 - 1) b2(it - 3);
+            __syncthreads();
+            __syncthreads();
+            if (it - 2 >= -1 && it - 2 <= nit2 - 1) halo_a2(it - 2);
+        }
+        return;
+    }
+
+    // ---- level-2 row waves v = 0..3: c of row Y2+2+v, collision of row
+    //      Y2 + ((v+2) & 3) (as step_tile's row waves)
+    const int v = w - 6;
+    const int gxl = x0 + lane;
+    R p1[9], p2[9], pg[9], ho[4];
+    auto a2 = [&](int j) {
+        const int Z = y0 + 4 * j;
+        const int y = Z + 2 + v;
+        ring_pull(lane + 3, y, p1, p2, pg);
+        const uint8_t m = sm.a.m[ring_slot(y, yb1) * LA::W + lane + 5];
+        const R a = sum_pop<P>(c, 0, p1), b = sum_pop<P>(c, 1, p2);
+        const int sl = ring_slot(y, y0) * LB::W + lane + 2;
+        const bool fl = m == 0;
+        sm.b.c1[sl] = fl ? a : R(0);
+        sm.b.c2[sl] = fl ? b : R(0);
+        sm.b.m[sl] = m;
+        if (v >= 2) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                sm.stash2[j & 1][v - 2][k][lane] = p1[k];
+                sm.stash2[j & 1][v - 2][9 + k][lane] = p2[k];
+                sm.stash2[j & 1][v - 2][18 + k][lane] = pg[k];
+            }
+        }
+        // history of the collision row of iteration j (read before level 1
+        // reuses its ring row)
+        const int yo = Z + ((v + 2) & 3);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ho[q] = sm.hist[pop_slot(yo, yb1)][q][lane];
+    };
+    auto c2 = [&](int j) {
+        const int yo = y0 + 4 * j + ((v + 2) & 3);
+        Stencil<R> s;
+        const int sl[3] = {ring_slot(yo - 1, y0), ring_slot(yo, y0), ring_slot(yo + 1, y0)};
+        const int ml[3] = {mu_slot(yo - 1, y0), mu_slot(yo, y0), mu_slot(yo + 1, y0)};
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            s.c1[r] = &sm.b.c1[sl[r] * LB::W + lane + 2];
+            s.c2[r] = &sm.b.c2[sl[r] * LB::W + lane + 2];
+            s.m[r] = &sm.b.m[sl[r] * LB::W + lane + 2];
+            s.mu1[r] = &sm.b.mu1[ml[r] * LB::MW + lane + 1];
+            s.mu2[r] = &sm.b.mu2[ml[r] * LB::MW + lane + 1];
+        }
+        s.mu3 = sm.b.mu3[ml[1] * LB::MW + lane + 1];
+        const unsigned mask = sm.b.nmask[ml[1] * LB::MW + lane + 1];
+        const bool live = yo < y0 + rows && !(mask & kSelfBit);
+        if (v >= 2) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                p1[k] = sm.stash2[(j - 1) & 1][v - 2][k][lane];
+                p2[k] = sm.stash2[(j - 1) & 1][v - 2][9 + k][lane];
+                pg[k] = sm.stash2[(j - 1) & 1][v - 2][18 + k][lane];
+            }
+        }
+        const Nb32 nb = make_nb32(g, gxl, wrapc(yo, g.ny));
+        const unsigned idx = nb.r0 + nb.x0;
+        const HbmSink<P> out{dst, c, hist_out, hstride, nb, live ? idx * 4u : kDiscard,
+                             live ? idx * 4u : kDiscard};
+        node_update<P, 0>(c, s, sm.mt, live, mask, p1, p2, pg, ho, out);
+    };
+    for (int it = -1; it <= itmax; ++it) {
+        __syncthreads();
+        if (it - 3 >= -1 && it - 3 <= nit2 - 1) b2(it - 3);
+        __syncthreads();
+        if (it - 3 >= 0 && it - 3 <= nit2 - 1) c2(it - 3);
+        __syncthreads();
+        if (it - 2 >= -1 && it - 2 <= nit2 - 1) a2(it - 2);
+    }
+}
+
+// Two steps of one lattice (descriptor 0 of the table) per launch, strips of
+// H rows: parity selects the source buffer as in step_kernel; the result
+// lands in the other buffer.
+template <int P>
+__global__ __launch_bounds__(kStep2Threads)
+void step2_kernel(const unsigned char* __restrict__ descs, int total_tiles, int parity, int H) {
+    using D = LatDesc<typename Tr<P>::R, typename Tr<P>::H>;
+    __shared__ Ring2<P> sm;
+    const D& d = *reinterpret_cast<const D*>(descs);
+    const Grid g = d.g;
+    const Consts<typename Tr<P>::R> c = d.c;
+    const int sb = (d.cur + parity) & 1;
+    step2_tile<P>(g, H, c, d.mat, d.mtab, d.buf[sb], d.buf[sb ^ 1], d.hist[sb], d.hist[sb ^ 1],
+                  tile_of(blockIdx.x, total_tiles), sm);
 }
 
 // ------------------------------------------------------------------- init
@@ -1460,6 +1968,12 @@ void step_pf(const void* descs, int ndesc, int total_tiles, int parity, hipStrea
 }
 
 template <int P>
+void step2_p(const void* descs, int total_tiles, int parity, int H, hipStream_t s) {
+    hipLaunchKernelGGL((step2_kernel<P>), dim3(total_tiles), dim3(kStep2Threads), 0, s,
+                       static_cast<const unsigned char*>(descs), total_tiles, parity, H);
+}
+
+template <int P>
 hipError_t step_p(unsigned features, const void* descs, int ndesc, int total_tiles, int parity,
                   hipStream_t s) {
     switch (features & (kFeatVel | kFeatLam)) {
@@ -1483,6 +1997,13 @@ hipError_t launch_step(int prec, unsigned features, const void* descs, int ndesc
         case P16: return step_p<P16>(features, descs, ndesc, total_tiles, parity, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_step2(int prec, const void* descs, int total_tiles, int parity, int rows,
+                        hipStream_t s) {
+    if (prec != P32) return hipErrorInvalidValue;
+    step2_p<P32>(descs, total_tiles, parity, rows, s);
+    return hipGetLastError();
 }
 
 template <int P>

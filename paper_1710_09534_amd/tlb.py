@@ -89,6 +89,7 @@ _SIGS = {
     "tlb_probe_bandwidth": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, _vp, _vp, C.c_size_t,
                                       _vp, C.c_int, _D]),
     "tlb_set_tile_rows": (C.c_int, [_vp, C.c_int]),
+    "tlb_set_pair_rows": (C.c_int, [_vp, C.c_int]),
     "tlb_autotune_rows": (C.c_int, [_vp, C.c_int, C.POINTER(C.c_int)]),
     "tlb_batch_table_bytes": (C.c_size_t, [C.c_int]),
     "tlb_batch_create": (C.c_int, [C.c_int, _vp, C.c_size_t, _vp, C.POINTER(_vp)]),
@@ -245,6 +246,9 @@ class Solver:
 
     def set_tile_rows(self, rows: int):
         _check(lib.tlb_set_tile_rows(self.ctx, int(rows)), self.ctx)
+
+    def set_pair_rows(self, rows: int):
+        _check(lib.tlb_set_pair_rows(self.ctx, int(rows)), self.ctx)
 
     @property
     def step_count(self) -> int:

@@ -159,11 +159,12 @@ def test_size_limit_boundary(prec, nx, elem, hist):
 
 def test_workspace_is_lattice_plus_modest_staging():
     """The staging area holds the 4 init fields, not a full copy of the
-    populations: workspace bytes per node stay close to the lattice's own."""
+    populations: workspace bytes per node stay close to the lattice's own
+    (two population buffers, the history planes of each, the material byte)."""
     from paper_1710_09534_amd import tlb
     n = 1024 * 2048
-    for prec, lattice in ((0, 2 * 27 * 8 + 4 * 8 + 1), (1, 2 * 27 * 4 + 4 * 4 + 1),
-                          (2, 2 * (16 * 2 + 11 * 4) + 4 * 4 + 1)):
+    for prec, lattice in ((0, 2 * 27 * 8 + 2 * 4 * 8 + 1), (1, 2 * 27 * 4 + 2 * 4 * 4 + 1),
+                          (2, 2 * (16 * 2 + 11 * 4) + 2 * 4 * 4 + 1)):
         per_node = tlb.tlb_workspace_bytes(1024, 2048, prec) / n
         assert lattice <= per_node <= lattice + 4 * 8 + 1, (prec, per_node)
 

@@ -1,0 +1,166 @@
+"""The two-step kernel (tlb_set_pair_rows): one launch advances the lattice by
+two time steps, the first level keeping its post-collision populations in
+LDS.  Every node of both levels goes through the same arithmetic as a step of
+the one-step kernel, so the state after any number of steps must be bitwise
+identical with pairs on and off: populations, fields and history (the mass
+read from it), on walls moving along both axes, scattered obstacles touching
+strip boundaries and the periodic seams, density contrast with gravity,
+ragged last strips and several strip heights, odd step counts (a pair
+sequence ending in a single step) and health checks that split pairs.  Also
+against the FP64 oracle within the FP32 bar, at the benchmark's 1024 x 2048
+lattice, and the argument checks of the entry point.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1710_09534_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tlb():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1710_09534_amd import tlb as t
+    return t
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _cases():
+    return {
+        "obstacles_128x96": lambda: W.random_obstacles(128, 96, seed=3, n_obstacles=30),
+        "channel_192x70_rho_g": lambda: W.random_fields(192, 70, seed=9, geometry="channel", U=0.01,
+                                                        rho=(10.0, 5.0, 1.0), gravity=(0.0, -1e-6)),
+        "box_64x40": lambda: W.random_fields(64, 40, seed=4, geometry="box", U=0.01),
+    }
+
+
+def _state(g):
+    return g.read_populations(), g.read_fields(), g.mass()
+
+
+def _assert_same(a, b, what):
+    pa, fa, ma = a
+    pb, fb, mb = b
+    assert np.array_equal(pa, pb), "%s: populations differ, max %.3e" % (
+        what, float(np.abs(pa - pb).max()))
+    for k in fa:
+        assert np.array_equal(fa[k], fb[k]), "%s: field %s differs" % (what, k)
+    assert np.array_equal(ma, mb), what
+
+
+@pytest.mark.parametrize("name", sorted(_cases()))
+@pytest.mark.parametrize("rows", [8, 12, 32])
+def test_pairs_bitwise_equal_single_steps(tlb, name, rows):
+    p = _cases()[name]()
+    steps = 9
+    _say("case %s fp32 pairs rows=%d %d steps" % (name, rows, steps))
+    ref = tlb.from_problem(p, "fp32")
+    ref.set_pair_rows(0)
+    ref.step(steps)
+    a = _state(ref)
+    g = tlb.from_problem(p, "fp32")
+    g.set_pair_rows(rows)
+    g.step(steps)
+    assert g.step_count == steps
+    _assert_same(_state(g), a, "%s rows=%d" % (name, rows))
+
+
+def test_pairs_split_by_health_checks(tlb):
+    """With a check every 3 steps, 10 steps run as pair, single (check),
+    pair, single (check), ...: still the same state, and stepping on from a
+    checkpoint taken mid-way continues identically."""
+    p = W.random_obstacles(128, 96, seed=5, n_obstacles=25)
+    _say("case %s pairs with check interval 3" % p["name"])
+    ref = tlb.from_problem(p, "fp32")
+    ref.set_pair_rows(0)
+    ref.set_check_interval(3)
+    ref.step(10)
+    g = tlb.from_problem(p, "fp32")
+    g.set_check_interval(3)
+    g.set_pair_rows(16)
+    g.step(10)
+    _assert_same(_state(g), _state(ref), "check interval 3")
+    blob = g.checkpoint_save()
+    h = tlb.from_problem(p, "fp32", init=False)
+    h.checkpoint_load(blob)
+    h.set_pair_rows(16)
+    h.step(5)
+    ref.step(5)
+    _assert_same(_state(h), _state(ref), "after checkpoint")
+
+
+def test_pairs_time_steps_equal_steps(tlb):
+    """tlb_time_steps advances the state with the same launches as tlb_step."""
+    p = W.random_obstacles(128, 96, seed=6, n_obstacles=20)
+    ref = tlb.from_problem(p, "fp32")
+    ref.set_pair_rows(0)
+    ref.step(8)
+    g = tlb.from_problem(p, "fp32")
+    g.set_pair_rows(24)
+    ms = g.time_steps(8)
+    assert ms > 0.0
+    _assert_same(_state(g), _state(ref), "time_steps")
+
+
+def test_pairs_against_oracle(tlb):
+    """300 steps of moving obstacles in pairs against the FP64 oracle: the
+    FP32 bar of the other parity tests (order parameters within 1e-4)."""
+    p = W.random_obstacles(192, 128, seed=8, n_obstacles=40)
+    o = oracle.Oracle(p)
+    o.init(p["c1"], p["c2"], p["ux"], p["uy"])
+    o.step(300)
+    fo = o.fields()
+    g = tlb.from_problem(p, "fp32")
+    g.set_pair_rows(32)
+    g.step(300)
+    fg = g.read_fields()
+    e = {k: float(np.abs(fg[k] - fo[k]).max()) for k in fo}
+    _say("pairs fp32 vs oracle: %s" % {k: "%.1e" % v for k, v in e.items()})
+    assert e["c1"] <= 1e-4 and e["c2"] <= 1e-4 and e["c3"] <= 1e-4, e
+
+
+def test_pairs_full_size_cylinder(tlb):
+    """The benchmark lattice (1024 x 2048 cylinder impact, FP32) with the
+    default pair strip height (the default mode): 21 steps equal 21 single
+    steps bitwise."""
+    p = W.cylinder_impact(nx=1024, ny=2048)
+    _say("case %s pairs default rows, 21 steps" % p["name"])
+    ref = tlb.from_problem(p, "fp32")
+    ref.set_pair_rows(0)
+    ref.step(21)
+    a = _state(ref)
+    del ref
+    g = tlb.from_problem(p, "fp32")
+    g.step(21)
+    _assert_same(_state(g), a, "cylinder 1024x2048")
+
+
+def test_pair_rows_arguments(tlb):
+    p = W.random_fields(64, 40, seed=4, geometry="box")
+    g64 = tlb.from_problem(p, "fp64")
+    with pytest.raises(tlb.TlbError):
+        g64.set_pair_rows(16)
+    g64.set_pair_rows(-1)   # the default; not applicable: one step per launch
+    g64.set_pair_rows(0)
+    g64.step(2)
+    g32 = tlb.from_problem(p, "fp32")
+    for bad in (4, 10, 8192, -2):
+        with pytest.raises(tlb.TlbError):
+            g32.set_pair_rows(bad)
+    q = W.random_fields(100, 40, seed=4, geometry="box")
+    g = tlb.from_problem(q, "fp32")
+    with pytest.raises(tlb.TlbError):
+        g.set_pair_rows(16)
+    h = tlb.from_problem(W.random_fields(64, 40, seed=4, geometry="box"), "fp16dev")
+    with pytest.raises(tlb.TlbError):
+        h.set_pair_rows(16)
