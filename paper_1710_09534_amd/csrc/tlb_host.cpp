@@ -52,8 +52,10 @@ Layout make_layout(int nx, int ny, int prec) {
     size_t o = 0;
     L.off_pop[0] = o; o += L.pop_bytes;
     L.off_pop[1] = o; o += L.pop_bytes;
-    L.off_hist[0] = o; o += L.hist_bytes;   // history of the populations in off_pop[0]
-    L.off_hist[1] = o; o += L.hist_bytes;   // and of off_pop[1]
+    // two sets of history planes: the two-step kernel reads one and writes
+    // the other (tlb_ctx::hcur names the current one)
+    L.off_hist[0] = o; o += L.hist_bytes;
+    L.off_hist[1] = o; o += L.hist_bytes;
     L.off_mat = o; o += align_up(L.npad, kAlign);
     L.off_mtab = o; o += align_up(kMatStride * (kMaxMaterials + 1) * sizeof(double), kAlign);
     L.off_desc = o; o += kDescBytes;
@@ -84,7 +86,8 @@ struct tlb_ctx {
     int64_t steps = 0;
     int64_t check_interval = 100;
     int64_t since_check = 0;
-    int cur = 0;  // lattice holding the current state
+    int cur = 0;   // lattice holding the current state
+    int hcur = 0;  // set of history planes holding the current history
     int pair_rows = -1;      // strip rows of the two-step kernel (0: one step per
                              // launch; -1: pair_auto_rows when the kernel applies)
     int pair_auto_rows = 0;  // default_pair_rows of this lattice
@@ -210,7 +213,7 @@ void set_grid(tlb_ctx* c, int rows) {
 
 // descriptor of ctx for the step kernel, with buf[cur] = current state at parity 0
 template <typename R, typename H>
-LatDesc<R, H> make_desc(tlb_ctx* c, const Consts<R>& k, int tile_begin, int cur) {
+LatDesc<R, H> make_desc(tlb_ctx* c, const Consts<R>& k, int tile_begin, int cur, int hcur) {
     static_assert(sizeof(LatDesc<R, H>) <= kDescBytes, "descriptor slot too small");
     LatDesc<R, H> d{};
     d.g = c->grid;
@@ -223,23 +226,25 @@ LatDesc<R, H> make_desc(tlb_ctx* c, const Consts<R>& k, int tile_begin, int cur)
     d.hist[1] = reinterpret_cast<H*>(c->ws + c->L.off_hist[1]);
     d.tile_begin = tile_begin;
     d.cur = cur;
+    d.hcur = hcur;
     return d;
 }
 
-// writes ctx's descriptor (tile_begin 0, cur 0) into host buffer `out`
-size_t fill_desc(tlb_ctx* c, void* out, int tile_begin, int cur) {
+// writes ctx's descriptor into host buffer `out`
+size_t fill_desc(tlb_ctx* c, void* out, int tile_begin, int cur, int hcur) {
     if (c->prec == P64) {
-        auto d = make_desc<double, double>(c, c->c64, tile_begin, cur);
+        auto d = make_desc<double, double>(c, c->c64, tile_begin, cur, hcur);
         std::memcpy(out, &d, sizeof(d));
         return sizeof(d);
     }
-    auto d = make_desc<float, float>(c, c->c32, tile_begin, cur);
+    auto d = make_desc<float, float>(c, c->c32, tile_begin, cur, hcur);
     std::memcpy(out, &d, sizeof(d));
     return sizeof(d);
 }
 
 tlb_status upload_desc(tlb_ctx* c) {
-    size_t n = fill_desc(c, c->desc_host, 0, 0);
+    // a lone context's launches pass cur and hcur in their parity argument
+    size_t n = fill_desc(c, c->desc_host, 0, 0, 0);
     hipError_t e = hipMemcpyAsync(c->ws + c->L.off_desc, c->desc_host, n, hipMemcpyHostToDevice,
                                   c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -251,7 +256,7 @@ int ntiles(const tlb_ctx* c) { return c->grid.tiles_x * c->grid.tiles_y; }
 
 tlb_status run_mass(tlb_ctx* c, hipStream_t s) {
     hipError_t e = launch_mass(c->prec, c->grid, reinterpret_cast<uint8_t*>(c->ws + c->L.off_mat),
-                               c->ws + c->L.off_hist[c->cur],
+                               c->ws + c->L.off_hist[c->hcur],
                                reinterpret_cast<double*>(c->ws + c->L.off_part),
                                reinterpret_cast<double*>(c->ws + c->L.off_result), s);
     if (e != hipSuccess) return dev_fail(c, e, "mass reduction");
@@ -477,6 +482,7 @@ tlb_status tlb_init_fields(tlb_ctx* c, const double* c1, const double* c2, const
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return dev_fail(c, e, "init kernel");
     c->cur = 0;
+    c->hcur = 0;
     c->steps = 0;
     c->since_check = 0;
     c->inited = true;
@@ -505,15 +511,17 @@ static tlb_status step_impl(tlb_ctx* c, int64_t nsteps, bool checks) {
         const int pr = c->pair_rows < 0 ? c->pair_auto_rows : c->pair_rows;
         const int n = (pr > 0 && pair_ok(c) && nsteps - s >= 2 && room) ? 2 : 1;
         hipError_t e;
+        const int parity = c->cur | (c->hcur << 1);
         if (n == 2) {
             const int tiles = c->grid.tiles_x * ((c->ny + pr - 1) / pr);
-            e = launch_step2(c->prec, c->ws + c->L.off_desc, tiles, c->cur, pr, c->stream);
+            e = launch_step2(c->prec, c->ws + c->L.off_desc, tiles, parity, pr, c->stream);
         } else {
-            e = launch_step(c->prec, features(c), c->ws + c->L.off_desc, 1, ntiles(c), c->cur,
+            e = launch_step(c->prec, features(c), c->ws + c->L.off_desc, 1, ntiles(c), parity,
                             c->stream);
         }
         if (e != hipSuccess) return dev_fail(c, e, "step kernel");
         c->cur = 1 - c->cur;
+        if (n == 2) c->hcur = 1 - c->hcur;   // the two-step kernel wrote the other set
         c->steps += n;
         s += n;
         if (checks && c->check_interval > 0 && (c->since_check += n) >= c->check_interval) {
@@ -668,7 +676,7 @@ tlb_status tlb_mass_noalloc(tlb_ctx* c, double* dev_out) {
     if (!c->inited) return fail(c, TLB_ESTATE, "init_fields must precede mass");
     if (!c->scratch) return fail(c, TLB_EDEVICE, "static scratch not resolved");
     hipError_t e = launch_mass(c->prec, c->grid, reinterpret_cast<uint8_t*>(c->ws + c->L.off_mat),
-                               c->ws + c->L.off_hist[c->cur], c->scratch, dev_out, c->stream);
+                               c->ws + c->L.off_hist[c->hcur], c->scratch, dev_out, c->stream);
     if (e != hipSuccess) return dev_fail(c, e, "mass reduction");
     return TLB_OK;
 }
@@ -696,7 +704,7 @@ tlb_status tlb_checkpoint_save(tlb_ctx* c, void* buf) {
     hipError_t e = hipMemcpyAsync(b + 64, c->ws + c->L.off_pop[c->cur], c->L.pop_bytes,
                                   hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(b + 64 + c->L.pop_bytes, c->ws + c->L.off_hist[c->cur], c->L.hist_bytes,
+        e = hipMemcpyAsync(b + 64 + c->L.pop_bytes, c->ws + c->L.off_hist[c->hcur], c->L.hist_bytes,
                            hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return dev_fail(c, e, "checkpoint save");
@@ -723,6 +731,7 @@ tlb_status tlb_checkpoint_load(tlb_ctx* c, const void* buf) {
     std::memcpy(c->c32.scale, b + 32, 3 * sizeof(float));
     std::memcpy(c->c32.iscale, b + 44, 3 * sizeof(float));
     c->cur = 0;
+    c->hcur = 0;
     c->steps = steps;
     c->since_check = 0;
     c->inited = true;
@@ -765,6 +774,7 @@ struct tlb_batch {
     int prec = -1;
     std::vector<tlb_ctx*> ctxs;
     std::vector<int> base_cur;         // each member's cur when the table was written
+    std::vector<int> base_hcur;        // and its hcur (batch steps keep it)
     std::vector<unsigned char> host;   // staged table
     int total_tiles = 0;
     unsigned features = 0;             // union of the members' step-kernel features
@@ -837,7 +847,8 @@ tlb_status tlb_batch_set(tlb_batch* b, tlb_ctx* const* ctxs, int n) {
     b->host.assign(size_t(n > 0 ? n : 1) * kDescBytes, 0);
     int begin = 0;
     for (int i = 0; i < n; ++i) {
-        fill_desc(ctxs[i], b->host.data() + size_t(i) * kDescBytes, begin, ctxs[i]->cur);
+        fill_desc(ctxs[i], b->host.data() + size_t(i) * kDescBytes, begin, ctxs[i]->cur,
+                  ctxs[i]->hcur);
         begin += ntiles(ctxs[i]);
     }
     if (n > 0) {
@@ -849,7 +860,11 @@ tlb_status tlb_batch_set(tlb_batch* b, tlb_ctx* const* ctxs, int n) {
     drop_graph(b);
     b->ctxs.assign(ctxs, ctxs + n);
     b->base_cur.resize(size_t(n));
-    for (int i = 0; i < n; ++i) b->base_cur[size_t(i)] = ctxs[i]->cur;
+    b->base_hcur.resize(size_t(n));
+    for (int i = 0; i < n; ++i) {
+        b->base_cur[size_t(i)] = ctxs[i]->cur;
+        b->base_hcur[size_t(i)] = ctxs[i]->hcur;
+    }
     b->prec = prec;
     b->total_tiles = tiles;
     b->features = feat;
@@ -888,7 +903,7 @@ tlb_status tlb_batch_step(tlb_batch* b, int64_t nsteps) {
     for (size_t i = 0; i < b->ctxs.size(); ++i) {
         const tlb_ctx* c = b->ctxs[i];
         if (c->diverged) return bfail(b, TLB_EDIVERGED, "a context has diverged");
-        if (((b->base_cur[i] + b->parity) & 1) != c->cur)
+        if (((b->base_cur[i] + b->parity) & 1) != c->cur || b->base_hcur[i] != c->hcur)
             return bfail(b, TLB_ESTATE, "a member was stepped outside the batch: call tlb_batch_set");
     }
     int64_t done = 0;

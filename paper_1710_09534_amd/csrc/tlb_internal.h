@@ -64,9 +64,10 @@ struct Grid {
 
 // Device descriptor of one lattice for the step kernel (R: arithmetic type,
 // H: history storage type).  buf[cur] holds the current state at the step
-// the launch's parity 0 refers to; hist[b] holds the history planes that
-// belong to the populations of buf[b] (a step reads both from one index and
-// writes both to the other).
+// the launch's parity 0 refers to.  Of the two sets of history planes,
+// hist[hcur ^ (bit 1 of the launch's parity)] holds the current history: the
+// one-step kernel updates it in place, the two-step kernel writes the other
+// set (another strip may still read the old one).
 template <typename R, typename H>
 struct LatDesc {
     Grid g;
@@ -77,6 +78,7 @@ struct LatDesc {
     H* hist[2];
     int tile_begin;   // prefix sum of the strip counts of the preceding lattices
     int cur;
+    int hcur;
 };
 // A descriptor table stores descriptor i at byte offset i * kDescBytes.
 constexpr size_t kDescBytes = 512;  // >= sizeof(LatDesc), a multiple of 256
@@ -85,7 +87,8 @@ constexpr size_t kDescBytes = 512;  // >= sizeof(LatDesc), a multiple of 256
 // Step kernel over a device table of descriptors (LatDesc<double,double> for
 // P64, LatDesc<float,float> otherwise); total_tiles = sum of strip counts;
 // features: bit 0 some lattice of the table has velocity boundary nodes,
-// bit 1 some lattice has a bulk energy with lambda > 0.
+// bit 1 some lattice has a bulk energy with lambda > 0; parity bit 0 selects
+// the population buffer, bit 1 the history set (see LatDesc).
 hipError_t launch_step(int prec, unsigned features, const void* descs, int ndesc,
                        int total_tiles, int parity, hipStream_t s);
 // Two steps of one lattice per launch (P32, a lattice without optional step

@@ -916,9 +916,8 @@ template <int P, unsigned F>
 __device__ __forceinline__ void step_tile(const Grid& g, const Consts<typename Tr<P>::R>& c,
                                           const uint8_t* __restrict__ mat,
                                           const double* __restrict__ mtab, PopBuf srcb,
-                                          PopBuf dstb, const typename Tr<P>::H* __restrict__ histi,
-                                          typename Tr<P>::H* __restrict__ histo, int t,
-                                          Ring<P>& sm) {
+                                          PopBuf dstb, typename Tr<P>::H* __restrict__ histp,
+                                          int t, Ring<P>& sm) {
     using R = typename Tr<P>::R;
     using HT = typename Tr<P>::H;
     using RG = Ring<P>;
@@ -993,8 +992,7 @@ __device__ __forceinline__ void step_tile(const Grid& g, const Consts<typename T
     const bool out_lane = x0 + lane < g.nx;
     const LatView<P> dst = lat_view<P>(dstb, g.npad);
     const unsigned hstride = unsigned(g.npad * long(sizeof(HT)));
-    const rsrc_t hist = make_rsrc(histi, 4u * hstride);      // history read (Eq. 19)
-    const rsrc_t hist_out = make_rsrc(histo, 4u * hstride);  // and written
+    const rsrc_t hist = make_rsrc(histp, 4u * hstride);   // history, updated in place (Eq. 19)
     if constexpr (P == P64) {
         // Two register sets of pulled populations alternate (the loop is
         // unrolled by two): phase A of iteration it consumes the set pulled
@@ -1095,7 +1093,7 @@ __device__ __forceinline__ void step_tile(const Grid& g, const Consts<typename T
                           fm);
                 __builtin_amdgcn_sched_barrier(0);
             }
-            const HbmSink<P> out{dst, c, hist_out, hstride, nb,
+            const HbmSink<P> out{dst, c, hist, hstride, nb,
                                  live ? idx * unsigned(sizeof(typename Tr<P>::S)) : kDiscard,
                                  live ? idx * 4u : kDiscard};
             node_update<P, F>(c, s, sm.mt, live, mask, u1, u2, gg, ho, out);
@@ -1220,7 +1218,7 @@ __device__ __forceinline__ void step_tile(const Grid& g, const Consts<typename T
                               nf2, nm);
                     __builtin_amdgcn_sched_barrier(0);
                 }
-                const HbmSink<P> out{dst, c, hist_out, hstride, nb,
+                const HbmSink<P> out{dst, c, hist, hstride, nb,
                                      live ? idx * unsigned(sizeof(typename Tr<P>::S)) : kDiscard,
                                      live ? idx * 4u : kDiscard};
                 node_update<P, F>(c, s, sm.mt, live, mask, cf1, cf2, gg, ho, out);
@@ -1262,8 +1260,9 @@ void step_kernel(const unsigned char* __restrict__ descs, int ndesc, int total_t
     const Grid g = d.g;
     const Consts<typename Tr<P>::R> c = d.c;
     const int sb = (d.cur + parity) & 1;
-    step_tile<P, F>(g, c, d.mat, d.mtab, d.buf[sb], d.buf[sb ^ 1], d.hist[sb], d.hist[sb ^ 1],
-                    L - d.tile_begin, sm);
+    const int hb = (d.hcur ^ (parity >> 1)) & 1;
+    step_tile<P, F>(g, c, d.mat, d.mtab, d.buf[sb], d.buf[sb ^ 1], d.hist[hb], L - d.tile_begin,
+                    sm);
 }
 
 // ------------------------------------------------------------ two-step march
@@ -1285,17 +1284,22 @@ void step_kernel(const unsigned char* __restrict__ descs, int ndesc, int total_t
 // Waves: 0-3 level-1 rows, 4 level-1 c on the 10 side columns, 5 level-1
 // collisions on the 6 side columns, 6-9 level-2 rows, 10 level-2 c on the 4
 // side columns.  Per iteration (four rows of each level) three barriers split
-//   slot 1: level-1 mu (waves 0-4) | level-2 mu (waves 6-10);
+//   slot 1: level-1 mu (waves 0-4), the side waves' loads (4: the pulls of
+//           their next c rows, 5: everything their collisions need) |
+//           level-2 mu (waves 6-10);
 //   slot 2: level-1 collisions into the ring (waves 0-3, 5) | level-2
 //           collisions to HBM (waves 6-9), so that the nine colliding waves
 //           share the SIMDs at once;
-//   slot 3: level-1 c of the next rows and their g / history loads (waves
-//           0-5) | level-2 c of the next rows from the ring (waves 6-10).
+//   slot 3: level-1 c of the next rows and the g / history loads of the row
+//           waves (waves 0-4) | level-2 c of the next rows from the ring
+//           (waves 6-10).
 // Level 2 reads ring rows only after the barrier that follows their level-1
 // collision, and a ring slot is rewritten only after its last reader (see
-// the row arithmetic at step2_tile).  With two slots (level-2 collision and
-// c in one, level-1 collision in the other) the levels' collisions ran one
-// after the other: 98.6 against 85.8 us per step on a 1024 x 2048 lattice.
+// the row arithmetic at step2_tile).  Measured on a 1024 x 2048 lattice:
+// with two slots (level-2 collision and c in one, level-1 collision in the
+// other) the levels' collisions ran one after the other, 98.6 against
+// 85.8 us per step; the side waves' loads in slot 3 made it the longer slot
+// (85.8 against 81.4 us with them in slot 1).
 // History planes: level 1 reads the
 // history of the launch's input state and passes its own (c, u) to level 2
 // through an LDS ring; level 2 writes the output history to the other
@@ -1406,7 +1410,7 @@ __device__ __forceinline__ void step2_tile(const Grid& g, int H, const Consts<ty
     const int nit1 = nit2 + 2;
     const int ylast1 = yb1 + rows1 + 1;                    // last level-1 row whose c is needed
     const int lane = threadIdx.x & (kTileX - 1);
-    const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kTileX);  // wave-uniform
+    const int w = threadIdx.x / kTileX;
     const LatView<P> src = lat_view<P>(srcb, g.npad);
     const rsrc_t matr = make_rsrc(mat, unsigned(g.npad));
     const auto* gmtab = (const __attribute__((address_space(1))) double*)mtab;
@@ -1449,7 +1453,7 @@ __device__ __forceinline__ void step2_tile(const Grid& g, int H, const Consts<ty
             const bool act = lane < 40;
             const int ccol = hc < 5 ? hc : kTileX + hc;
             const int gx = wrapc(x0 - 5 + ccol, g.nx);
-            auto halo_a = [&](int it) {
+            auto halo_c = [&](int it) {
                 const int Y = yb1 + 4 * it;
                 const R a = sum_pop<P>(c, 0, nf1), b = sum_pop<P>(c, 1, nf2);
                 if (act) {
@@ -1459,24 +1463,30 @@ __device__ __forceinline__ void step2_tile(const Grid& g, int H, const Consts<ty
                     sm.a.c2[sl] = fl ? b : R(0);
                     sm.a.m[sl] = nm;
                 }
-                pull_f<P>(g, c, src, matr, gx, wrapc(Y + 6 + hr, g.ny), act && Y + 6 + hr <= ylast1,
+            };
+            // pulls for the c rows of iteration it
+            auto halo_pull = [&](int it) {
+                const int Y = yb1 + 4 * it;
+                pull_f<P>(g, c, src, matr, gx, wrapc(Y + 2 + hr, g.ny), act && Y + 2 + hr <= ylast1,
                           nf1, nf2, nm);
             };
-            pull_f<P>(g, c, src, matr, gx, wrapc(yb1 - 2 + hr, g.ny), act, nf1, nf2, nm);
-            halo_a(-1);
+            halo_pull(-1);
+            halo_c(-1);
             for (int it = -1; it <= itmax; ++it) {
                 __syncthreads();
                 if (it <= nit1 - 1) b1(it);
+                // pulls for the c rows of it + 1, formed in slot 3
+                if (it + 1 <= nit1 - 1) halo_pull(it + 1);
                 __syncthreads();
                 __syncthreads();
-                if (it + 1 <= nit1 - 1) halo_a(it + 1);
+                if (it + 1 <= nit1 - 1) halo_c(it + 1);
             }
             return;
         }
         if (w == 5) {
             // collisions of the 6 side columns x0-3 .. x0-1, x0+64 .. x0+66
             // (ring columns 0..2, 67..69), lane = column + 6 * (row - Y1);
-            // their pulls, g and history are loaded one slot ahead
+            // their pulls, g and history are loaded in slot 1, one slot ahead
             const int hc = lane % 6;
             const int hr = lane / 6;
             const bool act = lane < 24;
@@ -1519,11 +1529,10 @@ __device__ __forceinline__ void step2_tile(const Grid& g, int H, const Consts<ty
             };
             for (int it = -1; it <= itmax; ++it) {
                 __syncthreads();
-                if (it <= nit1 - 1) b1(it);
+                if (it >= 0 && it <= nit1 - 1) side_a(it);
                 __syncthreads();
                 if (it >= 0 && it <= nit1 - 1) side_c(it);
                 __syncthreads();
-                if (it + 1 <= nit1 - 1) side_a(it + 1);
             }
             return;
         }
@@ -1744,7 +1753,8 @@ void step2_kernel(const unsigned char* __restrict__ descs, int total_tiles, int 
     const Grid g = d.g;
     const Consts<typename Tr<P>::R> c = d.c;
     const int sb = (d.cur + parity) & 1;
-    step2_tile<P>(g, H, c, d.mat, d.mtab, d.buf[sb], d.buf[sb ^ 1], d.hist[sb], d.hist[sb ^ 1],
+    const int hb = (d.hcur ^ (parity >> 1)) & 1;
+    step2_tile<P>(g, H, c, d.mat, d.mtab, d.buf[sb], d.buf[sb ^ 1], d.hist[hb], d.hist[hb ^ 1],
                   tile_of(blockIdx.x, total_tiles), sm);
 }
 
