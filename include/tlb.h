@@ -217,8 +217,9 @@ tlb_status tlb_checkpoint_bytes(const tlb_ctx* ctx, size_t* bytes);
 tlb_status tlb_checkpoint_save(tlb_ctx* ctx, void* host_buf);
 tlb_status tlb_checkpoint_load(tlb_ctx* ctx, const void* host_buf);
 
-/* Average device time of one step kernel over nsteps back-to-back launches
- * (HIP events on the context's stream; advances the state by nsteps). */
+/* Average device time per step over nsteps steps launched back to back
+ * (HIP events on the context's stream; advances the state by nsteps; two
+ * steps per launch where tlb_set_pair_rows applies, without health checks). */
 tlb_status tlb_time_steps(tlb_ctx* ctx, int64_t nsteps, double* ms_per_step);
 
 /* Rows of the strip one workgroup of the step kernel marches through

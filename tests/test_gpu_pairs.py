@@ -75,6 +75,22 @@ def test_pairs_bitwise_equal_single_steps(tlb, name, rows):
     _assert_same(_state(g), a, "%s rows=%d" % (name, rows))
 
 
+@pytest.mark.parametrize("geometry,ny", [("channel", 12), ("periodic", 16)])
+def test_pairs_short_lattices(tlb, geometry, ny):
+    """Lattices shorter than a strip's frame (a 8-row strip's first level
+    spans 16 rows): the first level wraps the periodic seam onto rows it also
+    computes elsewhere in the ring; still bitwise equal to single steps."""
+    p = W.random_fields(128, ny, seed=11, geometry=geometry, U=0.01)
+    _say("case %s pairs rows=8, 7 steps" % p["name"])
+    ref = tlb.from_problem(p, "fp32")
+    ref.set_pair_rows(0)
+    ref.step(7)
+    g = tlb.from_problem(p, "fp32")
+    g.set_pair_rows(8)
+    g.step(7)
+    _assert_same(_state(g), _state(ref), "%s ny=%d" % (geometry, ny))
+
+
 def test_pairs_split_by_health_checks(tlb):
     """With a check every 3 steps, 10 steps run as pair, single (check),
     pair, single (check), ...: still the same state, and stepping on from a
