@@ -53,11 +53,14 @@ def test_traffic_is_reported_only_for_the_profiled_kernel_source(monkeypatch):
         t = bench.measured_traffic(p)
         e = d["precisions"][p]
         assert t == e["traffic_bytes_per_launch"]
-        # the summary's own bookkeeping: read + write, each at least the
-        # algorithmic bytes (the counters cannot see less than the kernel moves)
+        # the summary's own bookkeeping: read + write, each at least one
+        # step's algorithmic bytes (a launch of k steps reads and writes the
+        # state at least once; the counters cannot see less than that)
         assert abs(t - (e["read_bytes"] + e["write_bytes"])) <= 1   # each rounded to a byte
-        assert e["read_bytes"] >= 0.99 * e["algorithmic_read_bytes"]
-        assert e["write_bytes"] >= 0.99 * e["algorithmic_write_bytes"]
+        k = e.get("steps_per_launch", 1)
+        assert k == (2 if p == "fp32" else 1)
+        assert e["read_bytes"] >= 0.99 * e["algorithmic_read_bytes"] / k
+        assert e["write_bytes"] >= 0.99 * e["algorithmic_write_bytes"] / k
     monkeypatch.setattr(bench, "kernel_sha", lambda: "0" * 16)
     assert bench.measured_traffic("fp32") is None
 
