@@ -167,10 +167,11 @@ tlb_status tlb_init_fields(tlb_ctx* ctx, const double* c1, const double* c2,
 /* Advance nsteps time steps, asynchronously on the context's stream.  Each
  * step is one fused pass: streaming with bounce-back (Eq. 44), moments
  * (Eqs. 13-15), wetting ghosts and chemical potentials (Eqs. 8, 20, 42),
- * forces (Eqs. 11-12), pressure (Eq. 13c), collision (Eq. 45).  Every
- * check_interval steps (tlb_set_check_interval, default 100) a mass/NaN
- * reduction runs on the device; a NaN seen by an earlier check makes this
- * call return TLB_EDIVERGED without stepping. */
+ * forces (Eqs. 11-12), pressure (Eq. 13c), collision (Eq. 45); where
+ * tlb_set_pair_rows applies, two such steps run in one launch (same
+ * results).  Every check_interval steps (tlb_set_check_interval, default
+ * 100) a mass/NaN reduction runs on the device; a NaN seen by an earlier
+ * check makes this call return TLB_EDIVERGED without stepping. */
 tlb_status tlb_step(tlb_ctx* ctx, int64_t nsteps);
 tlb_status tlb_set_check_interval(tlb_ctx* ctx, int64_t interval); /* 0 = never */
 int64_t    tlb_step_count(const tlb_ctx* ctx);
