@@ -58,13 +58,9 @@ def kernel_sha() -> str:
 
 def steps_per_launch(problem, precision: str) -> int:
     """Steps one launch of the dominant kernel advances: 2 where the library
-    uses its two-step kernel by default (FP32, no optional step parts, nx a
-    multiple of 64, a lattice that gives every compute unit a 64-row strip),
-    else 1."""
+    uses its two-step kernel by default (FP32, nx a multiple of 64, a lattice
+    that gives every compute unit a 64-row strip), else 1."""
     if precision != "fp32" or problem["nx"] % 64:
-        return 1
-    fl = problem["fluid"]
-    if fl.get("lambda", 0.0) or any(m.get("kind", 0) != 0 for m in problem["mats"]):
         return 1
     cus = 256
     try:
@@ -561,7 +557,7 @@ def main():
     # per launch: spl steps' algorithmic bytes over spl steps' kernel time
     achieved = alg / (head["kernel_ms"] * 1e-3) / 1e9
     traffic = measured_traffic(args.precision)
-    kname = ("step2_kernel<1> (two steps per launch, fp32 populations)" if spl == 2 else
+    kname = ("step2_kernel<1, 0u> (two steps per launch, fp32 populations)" if spl == 2 else
              "step_kernel<%d> (%s populations)" % ({"fp64": 0, "fp32": 1, "fp16dev": 2}[args.precision],
                                                    args.precision))
     out = {

@@ -242,9 +242,10 @@ tlb_status tlb_set_tile_rows(tlb_ctx* ctx, int rows);
  * once per two steps.  rows: a multiple of 4 in [8, 4096]; 0 turns it off
  * (one step per launch); -1, the default, picks the tallest of 256, 128, 64
  * rows that still gives each compute unit a strip (off for smaller
- * lattices).  Applies to FP32 populations without velocity boundary nodes
- * and with lambda = 0, on lattices whose nx is a multiple of 64; any other
- * context steps one step per launch, and returns TLB_EINVAL for rows > 0. */
+ * lattices).  Applies to FP32 populations on lattices whose nx is a
+ * multiple of 64 (with every optional part: velocity boundaries, lambda > 0,
+ * gravity); any other context steps one step per launch, and returns
+ * TLB_EINVAL for rows > 0. */
 tlb_status tlb_set_pair_rows(tlb_ctx* ctx, int rows);
 
 /* Picks the strip height with the shortest step among candidate values

@@ -496,11 +496,9 @@ static unsigned features(const tlb_ctx* c) {
     return (c->c64.nee != 0u ? 1u : 0u) | (c->fl.lambda != 0.0 ? 2u : 0u);
 }
 
-// The two-step kernel serves FP32 lattices without optional step parts whose
-// width is a multiple of 64 columns.
-static bool pair_ok(const tlb_ctx* c) {
-    return c->prec == P32 && features(c) == 0u && c->nx % kTileX == 0;
-}
+// The two-step kernel serves FP32 lattices whose width is a multiple of 64
+// columns.
+static bool pair_ok(const tlb_ctx* c) { return c->prec == P32 && c->nx % kTileX == 0; }
 
 static tlb_status step_impl(tlb_ctx* c, int64_t nsteps, bool checks) {
     for (int64_t s = 0; s < nsteps;) {
@@ -514,7 +512,8 @@ static tlb_status step_impl(tlb_ctx* c, int64_t nsteps, bool checks) {
         const int parity = c->cur | (c->hcur << 1);
         if (n == 2) {
             const int tiles = c->grid.tiles_x * ((c->ny + pr - 1) / pr);
-            e = launch_step2(c->prec, c->ws + c->L.off_desc, tiles, parity, pr, c->stream);
+            e = launch_step2(c->prec, features(c), c->ws + c->L.off_desc, tiles, parity, pr,
+                             c->stream);
         } else {
             e = launch_step(c->prec, features(c), c->ws + c->L.off_desc, 1, ntiles(c), parity,
                             c->stream);
@@ -576,8 +575,7 @@ tlb_status tlb_set_pair_rows(tlb_ctx* c, int rows) {
     if (rows < 8 || rows > 4096 || rows % 4)
         return fail(c, TLB_EINVAL, "pair strip rows must be 0, -1 or a multiple of 4 in [8, 4096]");
     if (!pair_ok(c))
-        return fail(c, TLB_EINVAL,
-                    "the two-step kernel needs FP32, no optional step parts and nx % 64 == 0");
+        return fail(c, TLB_EINVAL, "the two-step kernel needs FP32 and nx % 64 == 0");
     c->pair_rows = rows;
     return TLB_OK;
 }

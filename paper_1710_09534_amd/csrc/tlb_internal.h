@@ -91,12 +91,13 @@ constexpr size_t kDescBytes = 512;  // >= sizeof(LatDesc), a multiple of 256
 // the population buffer, bit 1 the history set (see LatDesc).
 hipError_t launch_step(int prec, unsigned features, const void* descs, int ndesc,
                        int total_tiles, int parity, hipStream_t s);
-// Two steps of one lattice per launch (P32, a lattice without optional step
-// parts, nx a multiple of 64): descs holds its descriptor, total_tiles its
-// strip count at strips of `rows` rows (a multiple of 4); the result lands in
-// the buffer the first of two step_kernel launches would have written.
-hipError_t launch_step2(int prec, const void* descs, int total_tiles, int parity, int rows,
-                        hipStream_t s);
+// Two steps of one lattice per launch (P32, nx a multiple of 64; features as
+// for launch_step): descs holds its descriptor, total_tiles its strip count at
+// strips of `rows` rows (a multiple of 4); the populations land in the buffer
+// the first of two step_kernel launches would have written, the history in
+// the set the launch's parity does not select.
+hipError_t launch_step2(int prec, unsigned features, const void* descs, int total_tiles,
+                        int parity, int rows, hipStream_t s);
 // `consts` points to a host Consts<double> (P64) or Consts<float> (P32, P16);
 // `mtab` to the device material table.
 hipError_t launch_init(int prec, const Grid& g, const void* consts, const uint8_t* mat,

@@ -1267,7 +1267,7 @@ void step_kernel(const unsigned char* __restrict__ descs, int ndesc, int total_t
 
 // ------------------------------------------------------------ two-step march
 // step2_kernel advances a lattice by two time steps in one pass over its
-// populations (FP32 storage, no optional parts).  A workgroup of eleven
+// populations (FP32 storage; optional parts F as in step_kernel).  A workgroup of eleven
 // waves marches a 64-column strip of rows [y0, y0 + H) at two time levels:
 //   level 1 collides rows [y0-4, y0+H+4) and columns [x0-3, x0+67) from the
 //     populations in HBM (the same phases as step_kernel) and keeps its
@@ -1389,7 +1389,7 @@ struct LdsSink {
 // slot 3 of index it (Y1-3 .. Y1+2) are not among them.  The history ring
 // row of a level-2 collision row is read with that row's c (slot 3, one
 // index before the collision), before level 1 rewrites it in slot 2.
-template <int P>
+template <int P, unsigned F>
 __device__ __forceinline__ void step2_tile(const Grid& g, int H, const Consts<typename Tr<P>::R>& c,
                                            const uint8_t* __restrict__ mat,
                                            const double* __restrict__ mtab, PopBuf srcb,
@@ -1428,7 +1428,7 @@ __device__ __forceinline__ void step2_tile(const Grid& g, int H, const Consts<ty
             const int r = threadIdx.x / LA::MW;
             const int mcol = threadIdx.x - r * LA::MW;
             const int y = yb1 + 4 * it + 1 + r;
-            if (y >= yb1 - 1) ring_mu<P, 0>(sm.a, sm.mt, c, y, yb1, mcol);
+            if (y >= yb1 - 1) ring_mu<P, F>(sm.a, sm.mt, c, y, yb1, mcol);
         }
     };
     auto b2 = [&](int j) {
@@ -1437,7 +1437,7 @@ __device__ __forceinline__ void step2_tile(const Grid& g, int H, const Consts<ty
             const int r = tt / LB::MW;
             const int mcol = tt - r * LB::MW;
             const int y = y0 + 4 * j + 1 + r;
-            if (y >= y0 - 1) ring_mu<P, 0>(sm.b, sm.mt, c, y, y0, mcol);
+            if (y >= y0 - 1) ring_mu<P, F>(sm.b, sm.mt, c, y, y0, mcol);
         }
     };
 
@@ -1525,7 +1525,7 @@ __device__ __forceinline__ void step2_tile(const Grid& g, int H, const Consts<ty
                 const bool live = act && yo < yb1 + rows1 && !(mask & kSelfBit);
                 const LdsSink<P> out{&sm.pop[0][0][0], &sm.hist[RG::PR][0][lane], pop_slot(yo, yb1),
                                      live ? pcol : RG::PW};
-                node_update<P, 0>(c, s, sm.mt, live, mask, nf1, nf2, gg, ho, out);
+                node_update<P, F>(c, s, sm.mt, live, mask, nf1, nf2, gg, ho, out);
             };
             for (int it = -1; it <= itmax; ++it) {
                 __syncthreads();
@@ -1610,7 +1610,7 @@ __device__ __forceinline__ void step2_tile(const Grid& g, int H, const Consts<ty
             const int ps = pop_slot(yo, yb1);
             const LdsSink<P> out{&sm.pop[0][0][0], &sm.hist[live ? ps : RG::PR][0][lane], ps,
                                  live ? lane + 3 : RG::PW};
-            node_update<P, 0>(c, s, sm.mt, live, mask, cf1, cf2, gg, ho, out);
+            node_update<P, F>(c, s, sm.mt, live, mask, cf1, cf2, gg, ho, out);
         };
         pull_f<P>(g, c, src, matr, gxl, wrapc(yb1 - 2 + w, g.ny), true, nf1, nf2, nm);
         phase_a(-1);
@@ -1729,7 +1729,7 @@ __device__ __forceinline__ void step2_tile(const Grid& g, int H, const Consts<ty
         const unsigned idx = nb.r0 + nb.x0;
         const HbmSink<P> out{dst, c, hist_out, hstride, nb, live ? idx * 4u : kDiscard,
                              live ? idx * 4u : kDiscard};
-        node_update<P, 0>(c, s, sm.mt, live, mask, p1, p2, pg, ho, out);
+        node_update<P, F>(c, s, sm.mt, live, mask, p1, p2, pg, ho, out);
     };
     for (int it = -1; it <= itmax; ++it) {
         __syncthreads();
@@ -1744,7 +1744,7 @@ __device__ __forceinline__ void step2_tile(const Grid& g, int H, const Consts<ty
 // Two steps of one lattice (descriptor 0 of the table) per launch, strips of
 // H rows: parity selects the source buffer as in step_kernel; the result
 // lands in the other buffer.
-template <int P>
+template <int P, unsigned F>
 __global__ __launch_bounds__(kStep2Threads)
 void step2_kernel(const unsigned char* __restrict__ descs, int total_tiles, int parity, int H) {
     using D = LatDesc<typename Tr<P>::R, typename Tr<P>::H>;
@@ -1754,7 +1754,7 @@ void step2_kernel(const unsigned char* __restrict__ descs, int total_tiles, int 
     const Consts<typename Tr<P>::R> c = d.c;
     const int sb = (d.cur + parity) & 1;
     const int hb = (d.hcur ^ (parity >> 1)) & 1;
-    step2_tile<P>(g, H, c, d.mat, d.mtab, d.buf[sb], d.buf[sb ^ 1], d.hist[hb], d.hist[hb ^ 1],
+    step2_tile<P, F>(g, H, c, d.mat, d.mtab, d.buf[sb], d.buf[sb ^ 1], d.hist[hb], d.hist[hb ^ 1],
                   tile_of(blockIdx.x, total_tiles), sm);
 }
 
@@ -1977,9 +1977,9 @@ void step_pf(const void* descs, int ndesc, int total_tiles, int parity, hipStrea
                        static_cast<const unsigned char*>(descs), ndesc, total_tiles, parity);
 }
 
-template <int P>
+template <int P, unsigned F>
 void step2_p(const void* descs, int total_tiles, int parity, int H, hipStream_t s) {
-    hipLaunchKernelGGL((step2_kernel<P>), dim3(total_tiles), dim3(kStep2Threads), 0, s,
+    hipLaunchKernelGGL((step2_kernel<P, F>), dim3(total_tiles), dim3(kStep2Threads), 0, s,
                        static_cast<const unsigned char*>(descs), total_tiles, parity, H);
 }
 
@@ -2009,10 +2009,15 @@ hipError_t launch_step(int prec, unsigned features, const void* descs, int ndesc
     }
 }
 
-hipError_t launch_step2(int prec, const void* descs, int total_tiles, int parity, int rows,
-                        hipStream_t s) {
+hipError_t launch_step2(int prec, unsigned features, const void* descs, int total_tiles,
+                        int parity, int rows, hipStream_t s) {
     if (prec != P32) return hipErrorInvalidValue;
-    step2_p<P32>(descs, total_tiles, parity, rows, s);
+    switch (features & (kFeatVel | kFeatLam)) {
+        case 0: step2_p<P32, 0>(descs, total_tiles, parity, rows, s); break;
+        case kFeatVel: step2_p<P32, kFeatVel>(descs, total_tiles, parity, rows, s); break;
+        case kFeatLam: step2_p<P32, kFeatLam>(descs, total_tiles, parity, rows, s); break;
+        default: step2_p<P32, kFeatVel | kFeatLam>(descs, total_tiles, parity, rows, s); break;
+    }
     return hipGetLastError();
 }
 

@@ -5,7 +5,8 @@ the one-step kernel, so the state after any number of steps must be bitwise
 identical with pairs on and off: populations, fields and history (the mass
 read from it), on walls moving along both axes, scattered obstacles touching
 strip boundaries and the periodic seams, density contrast with gravity,
-ragged last strips and several strip heights, odd step counts (a pair
+the bulk energy with lambda > 0, velocity boundary nodes, ragged last strips
+and several strip heights, odd step counts (a pair
 sequence ending in a single step) and health checks that split pairs.  Also
 against the FP64 oracle within the FP32 bar, at the benchmark's 1024 x 2048
 lattice, and the argument checks of the entry point.
@@ -35,12 +36,22 @@ def _say(msg):
     sys.stdout.flush()
 
 
+def _with_lambda(p, lam):
+    p["fluid"] = dict(p["fluid"], **{"lambda": lam})
+    return p
+
+
 def _cases():
     return {
         "obstacles_128x96": lambda: W.random_obstacles(128, 96, seed=3, n_obstacles=30),
         "channel_192x70_rho_g": lambda: W.random_fields(192, 70, seed=9, geometry="channel", U=0.01,
                                                         rho=(10.0, 5.0, 1.0), gravity=(0.0, -1e-6)),
         "box_64x40": lambda: W.random_fields(64, 40, seed=4, geometry="box", U=0.01),
+        # the optional parts: bulk energy with lambda > 0 (Eqs. 5-6), and
+        # velocity boundary nodes (Eqs. 51-53) in the top row
+        "lambda_128x96": lambda: _with_lambda(
+            W.random_fields(128, 96, seed=5, geometry="channel", U=0.01), 0.05),
+        "velocity_448x72": lambda: W.nee_shear(nx=448, ny=72, R_core=10.0, R_shell=24.0, offset=3.0),
     }
 
 
@@ -180,3 +191,5 @@ def test_pair_rows_arguments(tlb):
     h = tlb.from_problem(W.random_fields(64, 40, seed=4, geometry="box"), "fp16dev")
     with pytest.raises(tlb.TlbError):
         h.set_pair_rows(16)
+    # optional step parts are served by the two-step kernel too
+    tlb.from_problem(W.nee_shear(nx=448, ny=72, R_core=10.0, R_shell=24.0), "fp32").set_pair_rows(16)
