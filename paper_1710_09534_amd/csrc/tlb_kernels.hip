@@ -1267,8 +1267,9 @@ void step_kernel(const unsigned char* __restrict__ descs, int ndesc, int total_t
 
 // ------------------------------------------------------------ two-step march
 // step2_kernel advances a lattice by two time steps in one pass over its
-// populations (FP32 storage; optional parts F as in step_kernel).  A workgroup of eleven
-// waves marches a 64-column strip of rows [y0, y0 + H) at two time levels:
+// populations (FP32 storage; optional parts F as in step_kernel).  A
+// workgroup of eleven waves marches a 64-column strip of rows [y0, y0 + H)
+// at two time levels:
 //   level 1 collides rows [y0-4, y0+H+4) and columns [x0-3, x0+67) from the
 //     populations in HBM (the same phases as step_kernel) and keeps its
 //     post-collision populations in an LDS ring of 8 rows (27 planes x 70
@@ -1300,10 +1301,10 @@ void step_kernel(const unsigned char* __restrict__ descs, int ndesc, int total_t
 // other) the levels' collisions ran one after the other, 98.6 against
 // 85.8 us per step; the side waves' loads in slot 3 made it the longer slot
 // (85.8 against 81.4 us with them in slot 1).
-// History planes: level 1 reads the
-// history of the launch's input state and passes its own (c, u) to level 2
-// through an LDS ring; level 2 writes the output history to the other
-// history buffer (another strip's level 1 may still read the input one).
+// History planes: level 1 reads the history of the launch's input state and
+// passes its own (c, u) to level 2 through an LDS ring; level 2 writes the
+// output history to the other history set (another strip's level 1 may
+// still read the input one).
 constexpr int kStep2Waves = 11;
 constexpr int kStep2Threads = kStep2Waves * kTileX;
 
