@@ -126,6 +126,38 @@ def test_pairs_split_by_health_checks(tlb):
     _assert_same(_state(h), _state(ref), "after checkpoint")
 
 
+def test_batch_after_pairs(tlb):
+    """A context left on its second history set by an odd number of two-step
+    launches joins a batch (one step per launch, history updated in place in
+    that set), and a second batch member is stepped outside the batch in
+    between, which the batch must refuse: the members end bitwise equal to
+    contexts stepped one step at a time throughout."""
+    p = W.random_obstacles(128, 96, seed=7, n_obstacles=20)
+    q = W.random_fields(192, 64, seed=2, geometry="channel", U=0.01)
+    refs = []
+    for prob in (p, q):
+        r = tlb.from_problem(prob, "fp32")
+        r.set_pair_rows(0)
+        r.step(9)
+        refs.append(_state(r))
+    a = tlb.from_problem(p, "fp32")
+    a.set_pair_rows(16)
+    a.step(2)                    # one two-step launch: current history is set 1
+    b = tlb.from_problem(q, "fp32")
+    b.set_pair_rows(0)
+    b.step(2)
+    batch = tlb.Batch(4)
+    batch.set([a, b])
+    batch.step(5)
+    batch.sync()
+    a.step(2)                    # outside the batch: another two-step launch
+    with pytest.raises(tlb.TlbError):
+        batch.step(1)            # a member moved on without the batch
+    b.step(2)
+    _assert_same(_state(a), refs[0], "pairs, batch, pairs")
+    _assert_same(_state(b), refs[1], "batch member")
+
+
 def test_pairs_time_steps_equal_steps(tlb):
     """tlb_time_steps advances the state with the same launches as tlb_step."""
     p = W.random_obstacles(128, 96, seed=6, n_obstacles=20)
