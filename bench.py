@@ -581,6 +581,11 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
+                     # measured HBM bytes per launch over the launch time: the
+                     # real traffic rate (about half the algorithmic one when a
+                     # launch covers two steps)
+                     "traffic_gbs": (round(traffic / (spl * head["kernel_ms"] * 1e-3) / 1e9, 1)
+                                     if traffic else None),
                      "kernel": kname, "steps_per_launch": spl,
                      "algorithmic_bytes_per_launch": spl * alg},
         "precisions": table,
