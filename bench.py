@@ -187,8 +187,9 @@ def leg_3d(tlb, torch, steps=100):
 
 def batching_leg(tlb, torch, precision="fp32", n_lattices=256, size=64, steps=200):
     """Many small lattices (the serving stream's most common size) advanced
-    one at a time versus together in one batched, graph-replayed launch per
-    step; the same lattices one at a time with the plain FP64 path are the
+    one at a time versus together in batched, graph-replayed launches (two
+    steps per launch, the batch default for FP32, and one step per launch);
+    the same lattices one at a time with the plain FP64 path are the
     reference."""
     from paper_1710_09534_amd import workloads as W
     rng = W.Rng(99)
@@ -205,7 +206,7 @@ def batching_leg(tlb, torch, precision="fp32", n_lattices=256, size=64, steps=20
     t_solo = time.perf_counter() - t0
     b = tlb.Batch(n_lattices)
     b.set(solvers)
-    b.use_graph(50)
+    b.use_graph(48)
     b.step(50)
     b.sync()
     t0 = time.perf_counter()
@@ -214,13 +215,23 @@ def batching_leg(tlb, torch, precision="fp32", n_lattices=256, size=64, steps=20
     t_batch = time.perf_counter() - t0
     # the same batch with strip heights from the batch autotuner
     rows = b.autotune_rows(10)
-    b.use_graph(50)
+    b.use_graph(48)
     b.step(50)
     b.sync()
     t0 = time.perf_counter()
     b.step(steps)
     b.sync()
     t_tuned = time.perf_counter() - t0
+    # the same batch at one step per launch (its default for FP32 members is
+    # two steps per launch)
+    b.set_pair_rows(0)
+    b.use_graph(48)
+    b.step(48)
+    b.sync()
+    t0 = time.perf_counter()
+    b.step(steps)
+    b.sync()
+    t_one = time.perf_counter() - t0
     del b, solvers
     solvers = [tlb.from_problem(p, "fp64") for p in probs]
     for s in solvers:
@@ -238,6 +249,7 @@ def batching_leg(tlb, torch, precision="fp32", n_lattices=256, size=64, steps=20
             "autotuned_rows": rows,
             "batched_autotuned_mlups": round(nodes * steps / t_tuned / 1e6, 1),
             "batched_mlups": round(nodes * steps / t_batch / 1e6, 1),
+            "batched_one_step_per_launch_mlups": round(nodes * steps / t_one / 1e6, 1),
             "speedup": round(t_solo / t_batch, 2),
             "one_at_a_time_fp64_mlups": round(nodes * steps / t_fp64 / 1e6, 1),
             "speedup_vs_fp64": round(t_fp64 / t_batch, 2)}

@@ -271,11 +271,23 @@ tlb_status tlb_batch_create(int max_lattices, void* dev_table, size_t bytes,
                             void* hip_stream, tlb_batch** out);
 /* sets the member contexts (synchronizes their streams); n may be 0 */
 tlb_status tlb_batch_set(tlb_batch* batch, tlb_ctx* const* ctxs, int n);
-/* captures `steps` (even) launches into a HIP graph replayed by
- * tlb_batch_step (0 = plain launches) */
+/* captures `steps` steps (even; a multiple of 4 while the batch takes two
+ * steps per launch, see tlb_batch_set_pair_rows) into a HIP graph replayed
+ * by tlb_batch_step (0 = plain launches) */
 tlb_status tlb_batch_use_graph(tlb_batch* batch, int steps);
 /* advances every member by nsteps, asynchronously on the batch stream */
 tlb_status tlb_batch_step(tlb_batch* batch, int64_t nsteps);
+/* Two steps per launch for the whole batch (results bitwise those of one
+ * step per launch of the same batch): when every member is FP32 with nx a
+ * multiple of 64, tlb_batch_step advances the members two steps per launch
+ * of the two-step kernel (tlb_set_pair_rows) over strips of `rows` rows of
+ * every member (rows: a multiple of 4 in [8, 4096]; -1, the default: each
+ * member's height up to 128 rows), and tlb_batch_use_graph then needs a
+ * multiple of 4 steps; with rows = 0, or any other member, one step per
+ * launch.  Re-registers the members (as tlb_batch_set) and drops a
+ * captured graph.  TLB_EINVAL bad rows, TLB_ESTATE if a member was stepped
+ * outside the batch. */
+tlb_status tlb_batch_set_pair_rows(tlb_batch* batch, int rows);
 tlb_status tlb_batch_sync(tlb_batch* batch);
 /* Strip heights of the members (the step kernel's tile shape), tuned for the
  * batched launch: members of equal height form a size class, and one pass

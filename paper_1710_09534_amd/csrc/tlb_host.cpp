@@ -91,6 +91,7 @@ struct tlb_ctx {
     int pair_rows = -1;      // strip rows of the two-step kernel (0: one step per
                              // launch; -1: pair_auto_rows when the kernel applies)
     int pair_auto_rows = 0;  // default_pair_rows of this lattice
+    int desc_pair_rows = 0;  // the strip rows in the uploaded device descriptor
     int n_mats = 0;
     double mtab_host[kMatStride * (kMaxMaterials + 1)] = {};
     double* health = nullptr;  // pinned host copy of the last mass result
@@ -213,7 +214,8 @@ void set_grid(tlb_ctx* c, int rows) {
 
 // descriptor of ctx for the step kernel, with buf[cur] = current state at parity 0
 template <typename R, typename H>
-LatDesc<R, H> make_desc(tlb_ctx* c, const Consts<R>& k, int tile_begin, int cur, int hcur) {
+LatDesc<R, H> make_desc(tlb_ctx* c, const Consts<R>& k, int tile_begin, int cur, int hcur,
+                        int pair_rows, int pair_tile_begin) {
     static_assert(sizeof(LatDesc<R, H>) <= kDescBytes, "descriptor slot too small");
     LatDesc<R, H> d{};
     d.g = c->grid;
@@ -227,24 +229,48 @@ LatDesc<R, H> make_desc(tlb_ctx* c, const Consts<R>& k, int tile_begin, int cur,
     d.tile_begin = tile_begin;
     d.cur = cur;
     d.hcur = hcur;
+    d.pair_rows = pair_rows;
+    d.pair_tile_begin = pair_tile_begin;
     return d;
 }
 
 // writes ctx's descriptor into host buffer `out`
-size_t fill_desc(tlb_ctx* c, void* out, int tile_begin, int cur, int hcur) {
+size_t fill_desc(tlb_ctx* c, void* out, int tile_begin, int cur, int hcur, int pair_rows = 0,
+                 int pair_tile_begin = 0) {
     if (c->prec == P64) {
-        auto d = make_desc<double, double>(c, c->c64, tile_begin, cur, hcur);
+        auto d = make_desc<double, double>(c, c->c64, tile_begin, cur, hcur, pair_rows,
+                                           pair_tile_begin);
         std::memcpy(out, &d, sizeof(d));
         return sizeof(d);
     }
-    auto d = make_desc<float, float>(c, c->c32, tile_begin, cur, hcur);
+    auto d = make_desc<float, float>(c, c->c32, tile_begin, cur, hcur, pair_rows, pair_tile_begin);
     std::memcpy(out, &d, sizeof(d));
     return sizeof(d);
 }
 
+// The two-step kernel serves FP32 lattices whose width is a multiple of 64
+// columns.
+bool pair_ok(const tlb_ctx* c) { return c->prec == P32 && c->nx % kTileX == 0; }
+
+// strip rows of a lone context's two-step launches (0: one step per launch)
+int pair_rows_of(const tlb_ctx* c) {
+    if (!pair_ok(c)) return 0;
+    return c->pair_rows < 0 ? c->pair_auto_rows : c->pair_rows;
+}
+
+// Default two-step strip rows of a batch member: the lattice's height up to
+// 128 rows (measured on batches of 64^2 .. 256^2 FP32 lattices: 64-row strips
+// for 64^2, 128 for 128^2 and 256^2 were the fastest of 32, 64 and 128).
+int batch_pair_rows(int ny) { return std::min(128, std::max(8, (ny + 3) / 4 * 4)); }
+
+int pair_tiles(const tlb_ctx* c, int rows) {
+    return rows > 0 ? c->grid.tiles_x * ((c->ny + rows - 1) / rows) : 0;
+}
+
 tlb_status upload_desc(tlb_ctx* c) {
     // a lone context's launches pass cur and hcur in their parity argument
-    size_t n = fill_desc(c, c->desc_host, 0, 0, 0);
+    c->desc_pair_rows = pair_rows_of(c);
+    size_t n = fill_desc(c, c->desc_host, 0, 0, 0, c->desc_pair_rows, 0);
     hipError_t e = hipMemcpyAsync(c->ws + c->L.off_desc, c->desc_host, n, hipMemcpyHostToDevice,
                                   c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -496,24 +522,23 @@ static unsigned features(const tlb_ctx* c) {
     return (c->c64.nee != 0u ? 1u : 0u) | (c->fl.lambda != 0.0 ? 2u : 0u);
 }
 
-// The two-step kernel serves FP32 lattices whose width is a multiple of 64
-// columns.
-static bool pair_ok(const tlb_ctx* c) { return c->prec == P32 && c->nx % kTileX == 0; }
-
 static tlb_status step_impl(tlb_ctx* c, int64_t nsteps, bool checks) {
     for (int64_t s = 0; s < nsteps;) {
         // two steps in one launch when the kernel applies and no health check
         // falls between them
         const bool room = !checks || c->check_interval <= 0 ||
                           c->check_interval - c->since_check >= 2;
-        const int pr = c->pair_rows < 0 ? c->pair_auto_rows : c->pair_rows;
-        const int n = (pr > 0 && pair_ok(c) && nsteps - s >= 2 && room) ? 2 : 1;
+        const int pr = pair_rows_of(c);
+        if (pr != c->desc_pair_rows) {   // the descriptor must carry the strip height
+            tlb_status st = upload_desc(c);
+            if (st != TLB_OK) return st;
+        }
+        const int n = (pr > 0 && nsteps - s >= 2 && room) ? 2 : 1;
         hipError_t e;
         const int parity = c->cur | (c->hcur << 1);
         if (n == 2) {
-            const int tiles = c->grid.tiles_x * ((c->ny + pr - 1) / pr);
-            e = launch_step2(c->prec, features(c), c->ws + c->L.off_desc, tiles, parity, pr,
-                             c->stream);
+            e = launch_step2(c->prec, features(c), c->ws + c->L.off_desc, 1, pair_tiles(c, pr),
+                             parity, c->stream);
         } else {
             e = launch_step(c->prec, features(c), c->ws + c->L.off_desc, 1, ntiles(c), parity,
                             c->stream);
@@ -568,16 +593,16 @@ tlb_status tlb_set_tile_rows(tlb_ctx* c, int rows) {
 
 tlb_status tlb_set_pair_rows(tlb_ctx* c, int rows) {
     if (!c) return fail(c, TLB_EINVAL, "null context");
-    if (rows == -1 || rows == 0) {
-        c->pair_rows = rows;
-        return TLB_OK;
+    if (rows != -1 && rows != 0) {
+        if (rows < 8 || rows > 4096 || rows % 4)
+            return fail(c, TLB_EINVAL,
+                        "pair strip rows must be 0, -1 or a multiple of 4 in [8, 4096]");
+        if (!pair_ok(c))
+            return fail(c, TLB_EINVAL, "the two-step kernel needs FP32 and nx % 64 == 0");
     }
-    if (rows < 8 || rows > 4096 || rows % 4)
-        return fail(c, TLB_EINVAL, "pair strip rows must be 0, -1 or a multiple of 4 in [8, 4096]");
-    if (!pair_ok(c))
-        return fail(c, TLB_EINVAL, "the two-step kernel needs FP32 and nx % 64 == 0");
     c->pair_rows = rows;
-    return TLB_OK;
+    // the device descriptor carries the strip height
+    return c->inited ? upload_desc(c) : TLB_OK;
 }
 
 tlb_status tlb_read_fields(tlb_ctx* c, uint32_t mask, double* out) {
@@ -777,6 +802,11 @@ struct tlb_batch {
     int total_tiles = 0;
     unsigned features = 0;             // union of the members' step-kernel features
     int parity = 0;                    // parity of the next step relative to the table
+    int pair_rows = -1;                // two-step strip rows requested (0: one step per launch,
+                                       // -1: each member's batch_pair_rows)
+    bool pairs = false;                // pair_rows > 0 and every member can take two steps
+    int pair_total_tiles = 0;          // sum of the members' two-step strips
+    int hparity = 0;                   // history set of the next launch relative to the table
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int graph_steps = 0;
@@ -843,12 +873,18 @@ tlb_status tlb_batch_set(tlb_batch* b, tlb_ctx* const* ctxs, int n) {
         if (hipStreamSynchronize(ctxs[i]->stream) != hipSuccess)
             return bfail(b, TLB_EDEVICE, "context stream sync failed");
     b->host.assign(size_t(n > 0 ? n : 1) * kDescBytes, 0);
-    int begin = 0;
+    bool pairs = b->pair_rows != 0 && n > 0;
+    for (int i = 0; i < n; ++i) pairs = pairs && pair_ok(ctxs[i]);
+    int begin = 0, pbegin = 0;
     for (int i = 0; i < n; ++i) {
+        const int pr = !pairs ? 0 : (b->pair_rows > 0 ? b->pair_rows : batch_pair_rows(ctxs[i]->ny));
         fill_desc(ctxs[i], b->host.data() + size_t(i) * kDescBytes, begin, ctxs[i]->cur,
-                  ctxs[i]->hcur);
+                  ctxs[i]->hcur, pr, pbegin);
         begin += ntiles(ctxs[i]);
+        pbegin += pair_tiles(ctxs[i], pr);
     }
+    b->pairs = pairs;
+    b->pair_total_tiles = pbegin;
     if (n > 0) {
         hipError_t e = hipMemcpyAsync(b->dev, b->host.data(), size_t(n) * kDescBytes,
                                       hipMemcpyHostToDevice, b->stream);
@@ -867,20 +903,49 @@ tlb_status tlb_batch_set(tlb_batch* b, tlb_ctx* const* ctxs, int n) {
     b->total_tiles = tiles;
     b->features = feat;
     b->parity = 0;
+    b->hparity = 0;
     return TLB_OK;
+}
+
+tlb_status tlb_batch_set_pair_rows(tlb_batch* b, int rows) {
+    if (!b) return bfail(b, TLB_EINVAL, "null batch");
+    if (rows != 0 && rows != -1 && (rows < 8 || rows > 4096 || rows % 4))
+        return bfail(b, TLB_EINVAL,
+                     "pair strip rows must be 0, -1 or a multiple of 4 in [8, 4096]");
+    b->pair_rows = rows;
+    if (b->ctxs.empty()) return TLB_OK;
+    // re-register the members: the table carries the strip layout
+    const std::vector<tlb_ctx*> members = b->ctxs;
+    for (size_t i = 0; i < members.size(); ++i)
+        if (((b->base_cur[i] + b->parity) & 1) != members[i]->cur ||
+            (b->base_hcur[i] ^ b->hparity) != members[i]->hcur)
+            return bfail(b, TLB_ESTATE, "a member was stepped outside the batch: call tlb_batch_set");
+    if (hipStreamSynchronize(b->stream) != hipSuccess)
+        return bfail(b, TLB_EDEVICE, "batch stream sync failed");
+    return tlb_batch_set(b, members.data(), int(members.size()));
 }
 
 // records `steps` (even) step launches starting at parity 0 into a graph
 tlb_status tlb_batch_use_graph(tlb_batch* b, int steps) {
     if (!b || steps < 0 || (steps & 1)) return bfail(b, TLB_EINVAL, "graph steps must be even and >= 0");
+    if (b->pairs && (steps & 3))
+        return bfail(b, TLB_EINVAL, "with two steps per launch, graph steps must be a multiple of 4");
     drop_graph(b);
     if (steps == 0 || b->ctxs.empty()) return TLB_OK;
     hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return bfail(b, TLB_EDEVICE, std::string("begin capture: ") + hipGetErrorString(e));
     hipError_t le = hipSuccess;
-    for (int s = 0; s < steps && le == hipSuccess; ++s)
-        le = launch_step(b->prec, b->features, b->dev, int(b->ctxs.size()), b->total_tiles, s & 1,
-                         b->stream);
+    if (b->pairs) {
+        // two steps per launch: steps / 2 launches, each turning over the
+        // population buffer and the history set
+        for (int s = 0; s < steps / 2 && le == hipSuccess; ++s)
+            le = launch_step2(b->prec, b->features, b->dev, int(b->ctxs.size()),
+                              b->pair_total_tiles, (s & 1) | ((s & 1) << 1), b->stream);
+    } else {
+        for (int s = 0; s < steps && le == hipSuccess; ++s)
+            le = launch_step(b->prec, b->features, b->dev, int(b->ctxs.size()), b->total_tiles,
+                             s & 1, b->stream);
+    }
     e = hipStreamEndCapture(b->stream, &b->graph);
     if (le != hipSuccess || e != hipSuccess) {
         drop_graph(b);
@@ -901,26 +966,38 @@ tlb_status tlb_batch_step(tlb_batch* b, int64_t nsteps) {
     for (size_t i = 0; i < b->ctxs.size(); ++i) {
         const tlb_ctx* c = b->ctxs[i];
         if (c->diverged) return bfail(b, TLB_EDIVERGED, "a context has diverged");
-        if (((b->base_cur[i] + b->parity) & 1) != c->cur || b->base_hcur[i] != c->hcur)
+        if (((b->base_cur[i] + b->parity) & 1) != c->cur || (b->base_hcur[i] ^ b->hparity) != c->hcur)
             return bfail(b, TLB_ESTATE, "a member was stepped outside the batch: call tlb_batch_set");
     }
     int64_t done = 0;
+    int launches = 0, pair_launches = 0;   // beyond the graph replays (which change neither)
     const int nd = int(b->ctxs.size());
     while (done < nsteps) {
         hipError_t e;
-        if (b->exec && (b->parity & 1) == 0 && nsteps - done >= b->graph_steps) {
+        if (b->exec && b->parity == 0 && b->hparity == 0 && nsteps - done >= b->graph_steps) {
             e = hipGraphLaunch(b->exec, b->stream);
             if (e != hipSuccess) return bfail(b, TLB_EDEVICE, std::string("graph launch: ") + hipGetErrorString(e));
             done += b->graph_steps;
-            continue;   // even step count: parity unchanged
+            continue;   // an even number of launches: parity and history set unchanged
         }
-        e = launch_step(b->prec, b->features, b->dev, nd, b->total_tiles, b->parity, b->stream);
+        const int parity = b->parity | (b->hparity << 1);
+        if (b->pairs && nsteps - done >= 2) {
+            e = launch_step2(b->prec, b->features, b->dev, nd, b->pair_total_tiles, parity,
+                             b->stream);
+            b->hparity ^= 1;
+            ++pair_launches;
+            done += 2;
+        } else {
+            e = launch_step(b->prec, b->features, b->dev, nd, b->total_tiles, parity, b->stream);
+            ++done;
+        }
         if (e != hipSuccess) return bfail(b, TLB_EDEVICE, std::string("batch step: ") + hipGetErrorString(e));
         b->parity ^= 1;
-        ++done;
+        ++launches;
     }
     for (tlb_ctx* c : b->ctxs) {
-        c->cur ^= int(nsteps & 1);
+        c->cur ^= launches & 1;
+        c->hcur ^= pair_launches & 1;
         c->steps += nsteps;
     }
     return TLB_OK;
@@ -938,6 +1015,15 @@ tlb_status tlb_batch_autotune_rows(tlb_batch* b, int steps_per_candidate, int* b
     if (b->ctxs.empty()) return bfail(b, TLB_ESTATE, "tlb_batch_set must precede autotune");
     static const int cand[] = {16, 24, 32, 48, 64, 96, 128};
     const std::vector<tlb_ctx*> members = b->ctxs;
+    // the candidates are strip heights of the one-step kernel: time it alone
+    // (the final registration restores two steps per launch)
+    const int pair_rows = b->pair_rows;
+    b->pair_rows = 0;
+    struct Restore {
+        tlb_batch* b;
+        int rows;
+        ~Restore() { b->pair_rows = rows; }
+    } restore{b, pair_rows};
     // size classes: members of the same height share a strip height
     std::vector<int> heights;
     for (tlb_ctx* c : members)
@@ -998,6 +1084,7 @@ tlb_status tlb_batch_autotune_rows(tlb_batch* b, int steps_per_candidate, int* b
         }
         rows[h] = best;
     }
+    b->pair_rows = pair_rows;
     tlb_status st = apply();
     if (st != TLB_OK) return st;
     if (best_rows) *best_rows = rows.empty() ? 0 : rows[0];
@@ -1020,31 +1107,29 @@ tlb_status tlb_autotune_rows(tlb_ctx* c, int steps_per_candidate, int* best_rows
     if (!c || steps_per_candidate <= 0) return fail(c, TLB_EINVAL, "bad arguments");
     if (!c->inited) return fail(c, TLB_ESTATE, "init_fields must precede autotune");
     static const int cand[] = {16, 24, 32, 48, 64, 96, 128};
-    int best = c->grid.tile_rows;
-    double best_ms = 1e30;
-    // the candidates are strip heights of the one-step kernel: time it alone
+    // the candidates are strip heights of the one-step kernel: time it alone,
+    // then restore the two-step setting (and the descriptor that carries it)
     const int pair_rows = c->pair_rows;
     c->pair_rows = 0;
-    struct Restore {
-        tlb_ctx* c;
-        int rows;
-        ~Restore() { c->pair_rows = rows; }
-    } restore{c, pair_rows};
+    int best = c->grid.tile_rows;
+    double best_ms = 1e30;
     const int limit = ((c->ny + 3) / 4) * 4;
+    tlb_status st = TLB_OK;
     for (int rows : cand) {
         if (rows > (limit < 16 ? 16 : limit)) break;
-        tlb_status st = tlb_set_tile_rows(c, rows);
-        if (st != TLB_OK) return st;
+        st = tlb_set_tile_rows(c, rows);
         double ms = 0.0;
-        st = tlb_time_steps(c, steps_per_candidate, &ms);
-        if (st != TLB_OK) return st;
+        if (st == TLB_OK) st = tlb_time_steps(c, steps_per_candidate, &ms);
+        if (st != TLB_OK) break;
         if (ms < best_ms) {
             best_ms = ms;
             best = rows;
         }
     }
-    tlb_status st = tlb_set_tile_rows(c, best);
+    c->pair_rows = pair_rows;
+    tlb_status st2 = tlb_set_tile_rows(c, st == TLB_OK ? best : c->grid.tile_rows);
     if (st != TLB_OK) return st;
+    if (st2 != TLB_OK) return st2;
     if (best_rows) *best_rows = best;
     return TLB_OK;
 }

@@ -79,6 +79,8 @@ struct LatDesc {
     int tile_begin;   // prefix sum of the strip counts of the preceding lattices
     int cur;
     int hcur;
+    int pair_rows;        // strip rows of the two-step kernel (0: not used)
+    int pair_tile_begin;  // prefix sum of the preceding lattices' two-step strips
 };
 // A descriptor table stores descriptor i at byte offset i * kDescBytes.
 constexpr size_t kDescBytes = 512;  // >= sizeof(LatDesc), a multiple of 256
@@ -91,13 +93,13 @@ constexpr size_t kDescBytes = 512;  // >= sizeof(LatDesc), a multiple of 256
 // the population buffer, bit 1 the history set (see LatDesc).
 hipError_t launch_step(int prec, unsigned features, const void* descs, int ndesc,
                        int total_tiles, int parity, hipStream_t s);
-// Two steps of one lattice per launch (P32, nx a multiple of 64; features as
-// for launch_step): descs holds its descriptor, total_tiles its strip count at
-// strips of `rows` rows (a multiple of 4); the populations land in the buffer
-// the first of two step_kernel launches would have written, the history in
-// the set the launch's parity does not select.
-hipError_t launch_step2(int prec, unsigned features, const void* descs, int total_tiles,
-                        int parity, int rows, hipStream_t s);
+// Two steps per launch over a table of ndesc lattices (P32, nx a multiple of
+// 64; features as for launch_step): each descriptor's pair_rows (a multiple
+// of 4) and pair_tile_begin give its strips, total_tiles their sum; the
+// populations land in the buffer the first of two step_kernel launches would
+// have written, the history in the set the launch's parity does not select.
+hipError_t launch_step2(int prec, unsigned features, const void* descs, int ndesc,
+                        int total_tiles, int parity, hipStream_t s);
 // `consts` points to a host Consts<double> (P64) or Consts<float> (P32, P16);
 // `mtab` to the device material table.
 hipError_t launch_init(int prec, const Grid& g, const void* consts, const uint8_t* mat,

@@ -1742,21 +1742,34 @@ __device__ __forceinline__ void step2_tile(const Grid& g, int H, const Consts<ty
     }
 }
 
-// Two steps of one lattice (descriptor 0 of the table) per launch, strips of
-// H rows: parity selects the source buffer as in step_kernel; the result
-// lands in the other buffer.
+// Two steps per launch for a table of lattices (one, or a batch): a
+// workgroup finds its lattice by binary search over the prefix-summed
+// two-step strip counts, as step_kernel does over its own strips; parity
+// selects the source buffer and history set as in step_kernel, and the
+// result lands in the other ones.
 template <int P, unsigned F>
 __global__ __launch_bounds__(kStep2Threads)
-void step2_kernel(const unsigned char* __restrict__ descs, int total_tiles, int parity, int H) {
+void step2_kernel(const unsigned char* __restrict__ descs, int ndesc, int total_tiles,
+                  int parity) {
     using D = LatDesc<typename Tr<P>::R, typename Tr<P>::H>;
+    auto desc = [&](int i) -> const D& {
+        return *reinterpret_cast<const D*>(descs + size_t(i) * kDescBytes);
+    };
     __shared__ Ring2<P> sm;
-    const D& d = *reinterpret_cast<const D*>(descs);
+    const int L = tile_of(blockIdx.x, total_tiles);
+    int lo = 0, hi = ndesc - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (desc(mid).pair_tile_begin <= L) lo = mid;
+        else hi = mid - 1;
+    }
+    const D& d = desc(lo);
     const Grid g = d.g;
     const Consts<typename Tr<P>::R> c = d.c;
     const int sb = (d.cur + parity) & 1;
     const int hb = (d.hcur ^ (parity >> 1)) & 1;
-    step2_tile<P, F>(g, H, c, d.mat, d.mtab, d.buf[sb], d.buf[sb ^ 1], d.hist[hb], d.hist[hb ^ 1],
-                  tile_of(blockIdx.x, total_tiles), sm);
+    step2_tile<P, F>(g, d.pair_rows, c, d.mat, d.mtab, d.buf[sb], d.buf[sb ^ 1], d.hist[hb],
+                     d.hist[hb ^ 1], L - d.pair_tile_begin, sm);
 }
 
 // ------------------------------------------------------------------- init
@@ -1979,9 +1992,9 @@ void step_pf(const void* descs, int ndesc, int total_tiles, int parity, hipStrea
 }
 
 template <int P, unsigned F>
-void step2_p(const void* descs, int total_tiles, int parity, int H, hipStream_t s) {
+void step2_p(const void* descs, int ndesc, int total_tiles, int parity, hipStream_t s) {
     hipLaunchKernelGGL((step2_kernel<P, F>), dim3(total_tiles), dim3(kStep2Threads), 0, s,
-                       static_cast<const unsigned char*>(descs), total_tiles, parity, H);
+                       static_cast<const unsigned char*>(descs), ndesc, total_tiles, parity);
 }
 
 template <int P>
@@ -2010,14 +2023,14 @@ hipError_t launch_step(int prec, unsigned features, const void* descs, int ndesc
     }
 }
 
-hipError_t launch_step2(int prec, unsigned features, const void* descs, int total_tiles,
-                        int parity, int rows, hipStream_t s) {
+hipError_t launch_step2(int prec, unsigned features, const void* descs, int ndesc,
+                        int total_tiles, int parity, hipStream_t s) {
     if (prec != P32) return hipErrorInvalidValue;
     switch (features & (kFeatVel | kFeatLam)) {
-        case 0: step2_p<P32, 0>(descs, total_tiles, parity, rows, s); break;
-        case kFeatVel: step2_p<P32, kFeatVel>(descs, total_tiles, parity, rows, s); break;
-        case kFeatLam: step2_p<P32, kFeatLam>(descs, total_tiles, parity, rows, s); break;
-        default: step2_p<P32, kFeatVel | kFeatLam>(descs, total_tiles, parity, rows, s); break;
+        case 0: step2_p<P32, 0>(descs, ndesc, total_tiles, parity, s); break;
+        case kFeatVel: step2_p<P32, kFeatVel>(descs, ndesc, total_tiles, parity, s); break;
+        case kFeatLam: step2_p<P32, kFeatLam>(descs, ndesc, total_tiles, parity, s); break;
+        default: step2_p<P32, kFeatVel | kFeatLam>(descs, ndesc, total_tiles, parity, s); break;
     }
     return hipGetLastError();
 }

@@ -98,6 +98,7 @@ _SIGS = {
     "tlb_batch_step": (C.c_int, [_vp, C.c_int64]),
     "tlb_batch_autotune_rows": (C.c_int, [_vp, C.c_int, C.POINTER(C.c_int)]),
     "tlb_batch_sync": (C.c_int, [_vp]),
+    "tlb_batch_set_pair_rows": (C.c_int, [_vp, C.c_int]),
     "tlb_batch_last_error": (C.c_char_p, [_vp]),
     "tlb_batch_destroy": (None, [_vp]),
     "tlb_server_set_check_steps": (C.c_int, [_vp, C.c_int64]),
@@ -349,6 +350,9 @@ class Batch:
 
     def use_graph(self, steps: int):
         self._check(lib.tlb_batch_use_graph(self.h, int(steps)))
+
+    def set_pair_rows(self, rows: int):
+        self._check(lib.tlb_batch_set_pair_rows(self.h, int(rows)))
 
     def step(self, n: int):
         self._check(lib.tlb_batch_step(self.h, int(n)))

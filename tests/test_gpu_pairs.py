@@ -158,6 +158,102 @@ def test_batch_after_pairs(tlb):
     _assert_same(_state(b), refs[1], "batch member")
 
 
+def _solo_refs(tlb, probs, precision, steps):
+    refs = []
+    for prob in probs:
+        r = tlb.from_problem(prob, precision)
+        r.set_pair_rows(0)
+        r.step(steps)
+        refs.append(_state(r))
+    return refs
+
+
+@pytest.mark.parametrize("rows", [16, 64])
+def test_batch_pairs_bitwise(tlb, rows):
+    """A batch of lattices of several sizes, geometries and optional parts,
+    two steps per launch over strips of `rows` rows of every member (taller
+    than some lattices): 9 batched steps (four two-step launches and one
+    single) equal the same batch stepped one step per launch.  (A batch that
+    mixes optional parts runs every member through the kernel instance with
+    all of them, so a plain member's reference is the batch, not the member
+    alone; the plain-only batches below compare with members alone.)"""
+    probs = [_cases()[k]() for k in sorted(_cases())] + [W.reduction_case(nx=64, ny=64)]
+    states = []
+    for pr in (0, rows):
+        members = [tlb.from_problem(p, "fp32") for p in probs]
+        batch = tlb.Batch(8)
+        batch.set(members)
+        batch.set_pair_rows(pr)
+        batch.step(9)
+        batch.sync()
+        states.append([_state(m) for m in members])
+    for p, a, b in zip(probs, states[1], states[0]):
+        _assert_same(a, b, "batch pairs rows=%d %s" % (rows, p["name"]))
+
+
+def test_batch_pairs_plain_members_equal_alone(tlb):
+    """Plain members (no optional part in the batch): two steps per launch in
+    the batch equal each member alone one step per launch."""
+    probs = [W.random_obstacles(128, 96, seed=3, n_obstacles=30),
+             W.random_fields(192, 70, seed=9, geometry="channel", U=0.01, rho=(10.0, 5.0, 1.0),
+                             gravity=(0.0, -1e-6)),
+             W.random_fields(64, 40, seed=4, geometry="box"), W.reduction_case(nx=64, ny=64)]
+    refs = _solo_refs(tlb, probs, "fp32", 9)
+    members = [tlb.from_problem(p, "fp32") for p in probs]
+    batch = tlb.Batch(4)
+    batch.set(members)
+    batch.set_pair_rows(32)
+    batch.step(9)
+    batch.sync()
+    for p, m, r in zip(probs, members, refs):
+        _assert_same(_state(m), r, "plain batch pairs %s" % p["name"])
+
+
+def test_batch_pairs_graph(tlb):
+    """Graph replay of two-step launches (a multiple of 4 steps) between
+    plain launches: 22 batched steps equal 22 single steps; a graph of 6
+    steps is refused while pairs are on."""
+    probs = [W.random_obstacles(128, 96, seed=12, n_obstacles=20), W.reduction_case(nx=64, ny=64)]
+    refs = _solo_refs(tlb, probs, "fp32", 22)
+    members = [tlb.from_problem(p, "fp32") for p in probs]
+    batch = tlb.Batch(2)
+    batch.set(members)
+    batch.set_pair_rows(32)
+    with pytest.raises(tlb.TlbError):
+        batch.use_graph(6)
+    batch.use_graph(8)
+    batch.step(1)      # off parity: plain launches until the next multiple of the graph
+    batch.step(21)
+    batch.sync()
+    for p, m, r in zip(probs, members, refs):
+        _assert_same(_state(m), r, "batch graph pairs %s" % p["name"])
+
+
+def test_batch_pairs_not_applicable(tlb):
+    """FP64 members (and an FP32 batch with a 100-column member) keep one
+    step per launch when pairs are asked for, with the same results."""
+    probs = [W.random_fields(64, 40, seed=4, geometry="box"), W.reduction_case(nx=64, ny=64)]
+    refs = _solo_refs(tlb, probs, "fp64", 5)
+    members = [tlb.from_problem(p, "fp64") for p in probs]
+    batch = tlb.Batch(2)
+    batch.set(members)
+    batch.set_pair_rows(16)
+    batch.step(5)
+    batch.sync()
+    for p, m, r in zip(probs, members, refs):
+        _assert_same(_state(m), r, "fp64 batch %s" % p["name"])
+    q = [W.random_fields(100, 40, seed=4, geometry="box"), W.reduction_case(nx=64, ny=64)]
+    refs = _solo_refs(tlb, q, "fp32", 5)
+    members = [tlb.from_problem(p, "fp32") for p in q]
+    batch = tlb.Batch(2)
+    batch.set_pair_rows(16)
+    batch.set(members)
+    batch.step(5)
+    batch.sync()
+    for p, m, r in zip(q, members, refs):
+        _assert_same(_state(m), r, "mixed-width fp32 batch %s" % p["name"])
+
+
 def test_pairs_time_steps_equal_steps(tlb):
     """tlb_time_steps advances the state with the same launches as tlb_step."""
     p = W.random_obstacles(128, 96, seed=6, n_obstacles=20)
