@@ -972,34 +972,45 @@ tlb_status tlb_batch_step(tlb_batch* b, int64_t nsteps) {
     int64_t done = 0;
     int launches = 0, pair_launches = 0;   // beyond the graph replays (which change neither)
     const int nd = int(b->ctxs.size());
+    // the members take the launches that went out, also when a later one fails
+    auto settle = [&]() {
+        for (tlb_ctx* c : b->ctxs) {
+            c->cur ^= launches & 1;
+            c->hcur ^= pair_launches & 1;
+            c->steps += done;
+        }
+    };
     while (done < nsteps) {
         hipError_t e;
         if (b->exec && b->parity == 0 && b->hparity == 0 && nsteps - done >= b->graph_steps) {
             e = hipGraphLaunch(b->exec, b->stream);
-            if (e != hipSuccess) return bfail(b, TLB_EDEVICE, std::string("graph launch: ") + hipGetErrorString(e));
+            if (e != hipSuccess) {
+                settle();
+                return bfail(b, TLB_EDEVICE, std::string("graph launch: ") + hipGetErrorString(e));
+            }
             done += b->graph_steps;
             continue;   // an even number of launches: parity and history set unchanged
         }
         const int parity = b->parity | (b->hparity << 1);
-        if (b->pairs && nsteps - done >= 2) {
+        const bool pair = b->pairs && nsteps - done >= 2;
+        if (pair)
             e = launch_step2(b->prec, b->features, b->dev, nd, b->pair_total_tiles, parity,
                              b->stream);
-            b->hparity ^= 1;
-            ++pair_launches;
-            done += 2;
-        } else {
+        else
             e = launch_step(b->prec, b->features, b->dev, nd, b->total_tiles, parity, b->stream);
-            ++done;
+        if (e != hipSuccess) {
+            settle();
+            return bfail(b, TLB_EDEVICE, std::string("batch step: ") + hipGetErrorString(e));
         }
-        if (e != hipSuccess) return bfail(b, TLB_EDEVICE, std::string("batch step: ") + hipGetErrorString(e));
+        if (pair) {
+            b->hparity ^= 1;   // the two-step kernel wrote the other history set
+            ++pair_launches;
+        }
+        done += pair ? 2 : 1;
         b->parity ^= 1;
         ++launches;
     }
-    for (tlb_ctx* c : b->ctxs) {
-        c->cur ^= launches & 1;
-        c->hcur ^= pair_launches & 1;
-        c->steps += nsteps;
-    }
+    settle();
     return TLB_OK;
 }
 
