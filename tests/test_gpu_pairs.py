@@ -86,11 +86,13 @@ def test_pairs_bitwise_equal_single_steps(tlb, name, rows):
     _assert_same(_state(g), a, "%s rows=%d" % (name, rows))
 
 
-@pytest.mark.parametrize("geometry,ny", [("channel", 12), ("periodic", 16)])
+@pytest.mark.parametrize("geometry,ny", [("channel", 12), ("periodic", 16), ("channel", 3),
+                                         ("periodic", 3), ("periodic", 5), ("channel", 6)])
 def test_pairs_short_lattices(tlb, geometry, ny):
     """Lattices shorter than a strip's frame (a 8-row strip's first level
     spans 16 rows): the first level wraps the periodic seam onto rows it also
-    computes elsewhere in the ring; still bitwise equal to single steps."""
+    computes elsewhere in the ring, several times over for lattices shorter
+    than the strip itself; still bitwise equal to single steps."""
     p = W.random_fields(128, ny, seed=11, geometry=geometry, U=0.01)
     _say("case %s pairs rows=8, 7 steps" % p["name"])
     ref = tlb.from_problem(p, "fp32")
