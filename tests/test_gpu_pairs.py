@@ -211,6 +211,25 @@ def test_batch_pairs_plain_members_equal_alone(tlb):
         _assert_same(_state(m), r, "plain batch pairs %s" % p["name"])
 
 
+def test_batch_pairs_default_rows_short_members(tlb):
+    """The batch default (each member's strip: its height rounded up to 4,
+    at least 8 and at most 128 rows) with members 3 and 5 rows high beside
+    taller ones: 9 batched steps equal each member alone one step per
+    launch."""
+    probs = [W.random_fields(128, 3, seed=21, geometry="periodic"),
+             W.random_fields(64, 5, seed=22, geometry="periodic"),
+             W.random_fields(128, 6, seed=23, geometry="channel", U=0.01),
+             W.random_obstacles(128, 96, seed=24, n_obstacles=20), W.reduction_case(nx=64, ny=64)]
+    refs = _solo_refs(tlb, probs, "fp32", 9)
+    members = [tlb.from_problem(p, "fp32") for p in probs]
+    batch = tlb.Batch(5)
+    batch.set(members)
+    batch.step(9)
+    batch.sync()
+    for p, m, r in zip(probs, members, refs):
+        _assert_same(_state(m), r, "default-row batch pairs %s" % p["name"])
+
+
 def test_batch_pairs_graph(tlb):
     """Graph replay of two-step launches (a multiple of 4 steps) between
     plain launches: 22 batched steps equal 22 single steps; a graph of 6
