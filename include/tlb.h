@@ -257,8 +257,9 @@ tlb_status tlb_autotune_rows(tlb_ctx* ctx, int steps_per_candidate, int* best_ro
 
 /* ---- batches: many independent lattices advanced by shared launches ----
  * A batch holds initialised contexts of one precision (any sizes, fluids and
- * geometries).  Each step is one launch of the step kernel over the strips of
- * all lattices, so small lattices fill the GPU together.  A lattice's result
+ * geometries).  Each launch covers the strips of all lattices (one step, or
+ * two for FP32 batches, see tlb_batch_set_pair_rows), so small lattices fill
+ * the GPU together.  A lattice's result
  * is bitwise the same alone or in any batch.  The caller owns the device
  * table (tlb_batch_table_bytes, 256-byte aligned) and the contexts; while a
  * context is in a batch it must not be stepped on its own (tlb_batch_step
@@ -275,14 +276,18 @@ tlb_status tlb_batch_set(tlb_batch* batch, tlb_ctx* const* ctxs, int n);
  * steps per launch, see tlb_batch_set_pair_rows) into a HIP graph replayed
  * by tlb_batch_step (0 = plain launches) */
 tlb_status tlb_batch_use_graph(tlb_batch* batch, int steps);
-/* advances every member by nsteps, asynchronously on the batch stream */
+/* advances every member by nsteps, asynchronously on the batch stream;
+ * TLB_ESTATE if a member was stepped outside the batch, TLB_EDIVERGED if a
+ * member's health check found a non-finite field, TLB_EDEVICE if a launch
+ * fails (the members then count the launches that went out before it) */
 tlb_status tlb_batch_step(tlb_batch* batch, int64_t nsteps);
 /* Two steps per launch for the whole batch (results bitwise those of one
  * step per launch of the same batch): when every member is FP32 with nx a
  * multiple of 64, tlb_batch_step advances the members two steps per launch
  * of the two-step kernel (tlb_set_pair_rows) over strips of `rows` rows of
  * every member (rows: a multiple of 4 in [8, 4096]; -1, the default: each
- * member's height up to 128 rows), and tlb_batch_use_graph then needs a
+ * member's height rounded up to a multiple of 4, at least 8 and at most 128
+ * rows), and tlb_batch_use_graph then needs a
  * multiple of 4 steps; with rows = 0, or any other member, one step per
  * launch.  Re-registers the members (as tlb_batch_set) and drops a
  * captured graph.  TLB_EINVAL bad rows, TLB_ESTATE if a member was stepped
