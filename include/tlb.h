@@ -242,10 +242,10 @@ tlb_status tlb_set_tile_rows(tlb_ctx* ctx, int rows);
  * once per two steps.  rows: a multiple of 4 in [8, 4096]; 0 turns it off
  * (one step per launch); -1, the default, picks the tallest of 256, 128, 64
  * rows that still gives each compute unit a strip (off for smaller
- * lattices).  Applies to FP32 populations on lattices whose nx is a
- * multiple of 64 (with every optional part: velocity boundaries, lambda > 0,
- * gravity); any other context steps one step per launch, and returns
- * TLB_EINVAL for rows > 0. */
+ * lattices).  Applies to FP32 populations, on lattices of any size (with
+ * every optional part: velocity boundaries, lambda > 0, gravity); a context
+ * of another precision steps one step per launch, and returns TLB_EINVAL for
+ * rows > 0. */
 tlb_status tlb_set_pair_rows(tlb_ctx* ctx, int rows);
 
 /* Picks the strip height with the shortest step among candidate values
@@ -282,13 +282,13 @@ tlb_status tlb_batch_use_graph(tlb_batch* batch, int steps);
  * fails (the members then count the launches that went out before it) */
 tlb_status tlb_batch_step(tlb_batch* batch, int64_t nsteps);
 /* Two steps per launch for the whole batch (results bitwise those of one
- * step per launch of the same batch): when every member is FP32 with nx a
- * multiple of 64, tlb_batch_step advances the members two steps per launch
+ * step per launch of the same batch): when every member is FP32,
+ * tlb_batch_step advances the members two steps per launch
  * of the two-step kernel (tlb_set_pair_rows) over strips of `rows` rows of
  * every member (rows: a multiple of 4 in [8, 4096]; -1, the default: each
  * member's height rounded up to a multiple of 4, at least 8 and at most 128
  * rows), and tlb_batch_use_graph then needs a
- * multiple of 4 steps; with rows = 0, or any other member, one step per
+ * multiple of 4 steps; with rows = 0, or a member of another precision, one step per
  * launch.  Re-registers the members (as tlb_batch_set) and drops a
  * captured graph.  TLB_EINVAL bad rows, TLB_ESTATE if a member was stepped
  * outside the batch. */

@@ -187,7 +187,7 @@ int default_rows(int nx, int ny, int prec, int cus) {
 // CU): the tallest of 256, 128, 64 rows that still gives every CU a strip;
 // 0 (one step per launch) for a lattice too small for that.
 int default_pair_rows(int nx, int ny, int cus) {
-    const int tx = nx / kTileX;
+    const int tx = (nx + kTileX - 1) / kTileX;
     static const int cand[] = {256, 128, 64};
     for (int rows : cand)
         if (tx * ((ny + rows - 1) / rows) >= cus) return rows;
@@ -248,9 +248,10 @@ size_t fill_desc(tlb_ctx* c, void* out, int tile_begin, int cur, int hcur, int p
     return sizeof(d);
 }
 
-// The two-step kernel serves FP32 lattices whose width is a multiple of 64
-// columns.
-bool pair_ok(const tlb_ctx* c) { return c->prec == P32 && c->nx % kTileX == 0; }
+// The two-step kernel serves FP32 lattices of any width (in a last strip
+// narrower than 64 columns the lanes past nx step the wrapped columns that
+// form the strip's right frame).
+bool pair_ok(const tlb_ctx* c) { return c->prec == P32; }
 
 // strip rows of a lone context's two-step launches (0: one step per launch)
 int pair_rows_of(const tlb_ctx* c) {
@@ -598,7 +599,7 @@ tlb_status tlb_set_pair_rows(tlb_ctx* c, int rows) {
             return fail(c, TLB_EINVAL,
                         "pair strip rows must be 0, -1 or a multiple of 4 in [8, 4096]");
         if (!pair_ok(c))
-            return fail(c, TLB_EINVAL, "the two-step kernel needs FP32 and nx % 64 == 0");
+            return fail(c, TLB_EINVAL, "the two-step kernel needs FP32 storage");
     }
     c->pair_rows = rows;
     // the device descriptor carries the strip height

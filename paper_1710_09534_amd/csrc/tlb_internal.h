@@ -93,8 +93,8 @@ constexpr size_t kDescBytes = 512;  // >= sizeof(LatDesc), a multiple of 256
 // the population buffer, bit 1 the history set (see LatDesc).
 hipError_t launch_step(int prec, unsigned features, const void* descs, int ndesc,
                        int total_tiles, int parity, hipStream_t s);
-// Two steps per launch over a table of ndesc lattices (P32, nx a multiple of
-// 64; features as for launch_step): each descriptor's pair_rows (a multiple
+// Two steps per launch over a table of ndesc lattices (P32, any width;
+// features as for launch_step): each descriptor's pair_rows (a multiple
 // of 4) and pair_tile_begin give its strips, total_tiles their sum; the
 // populations land in the buffer the first of two step_kernel launches would
 // have written, the history in the set the launch's parity does not select.

@@ -1539,8 +1539,10 @@ __device__ __forceinline__ void step2_tile(const Grid& g, int H, const Consts<ty
         }
 
         // ---- level-1 row waves: columns x0 .. x0+63 (c ring column lane+5,
-        //      mu column lane+4, population ring column lane+3)
-        const int gxl = x0 + lane;
+        //      mu column lane+4, population ring column lane+3).  In a last
+        //      strip narrower than 64 columns the lanes past nx step the
+        //      wrapped columns 0, 1, 2, ..., which are that strip's right frame.
+        const int gxl = wrapc(x0 + lane, g.nx);
         R cf1[9], cf2[9], gg[9], ho[4];
         int yo = 0;
         auto phase_a = [&](int it) {
@@ -1675,7 +1677,8 @@ __device__ __forceinline__ void step2_tile(const Grid& g, int H, const Consts<ty
     // ---- level-2 row waves v = 0..3: c of row Y2+2+v, collision of row
     //      Y2 + ((v+2) & 3) (as step_tile's row waves)
     const int v = w - 6;
-    const int gxl = x0 + lane;
+    const int gxl = wrapc(x0 + lane, g.nx);
+    const bool out_lane = x0 + lane < g.nx;     // lanes past nx store nothing
     R p1[9], p2[9], pg[9], ho[4];
     auto a2 = [&](int j) {
         const int Z = y0 + 4 * j;
@@ -1717,7 +1720,7 @@ __device__ __forceinline__ void step2_tile(const Grid& g, int H, const Consts<ty
         }
         s.mu3 = sm.b.mu3[ml[1] * LB::MW + lane + 1];
         const unsigned mask = sm.b.nmask[ml[1] * LB::MW + lane + 1];
-        const bool live = yo < y0 + rows && !(mask & kSelfBit);
+        const bool live = yo < y0 + rows && out_lane && !(mask & kSelfBit);
         if (v >= 2) {
 #pragma unroll
             for (int k = 0; k < 9; ++k) {

@@ -86,6 +86,52 @@ def test_pairs_bitwise_equal_single_steps(tlb, name, rows):
     _assert_same(_state(g), a, "%s rows=%d" % (name, rows))
 
 
+def _ragged_cases():
+    return {
+        "obstacles_100x96": lambda: W.random_obstacles(100, 96, seed=31, n_obstacles=20),
+        "channel_130x70_rho_g": lambda: W.random_fields(130, 70, seed=32, geometry="channel", U=0.01,
+                                                        rho=(10.0, 5.0, 1.0), gravity=(0.0, -1e-6)),
+        "box_40x24": lambda: W.random_fields(40, 24, seed=33, geometry="box", U=0.01),
+        "periodic_127x33": lambda: W.random_fields(127, 33, seed=34, geometry="periodic"),
+        "periodic_5x17": lambda: W.random_fields(5, 17, seed=35, geometry="periodic"),
+        "lambda_150x40": lambda: _with_lambda(
+            W.random_fields(150, 40, seed=36, geometry="channel", U=0.01), 0.05),
+        "velocity_430x72": lambda: W.nee_shear(nx=430, ny=72, R_core=10.0, R_shell=24.0, offset=3.0),
+    }
+
+
+@pytest.mark.parametrize("name", sorted(_ragged_cases()))
+@pytest.mark.parametrize("rows", [8, 32])
+def test_pairs_ragged_widths(tlb, name, rows):
+    """Widths that are not a multiple of 64 (and one narrower than a strip):
+    in the last strip the lanes past nx step the wrapped columns that are the
+    strip's right frame, and store nothing; 7 steps (three two-step launches
+    and one single) are bitwise those of 7 single steps."""
+    p = _ragged_cases()[name]()
+    _say("case %s pairs rows=%d, 7 steps" % (p["name"], rows))
+    ref = tlb.from_problem(p, "fp32")
+    ref.set_pair_rows(0)
+    ref.step(7)
+    g = tlb.from_problem(p, "fp32")
+    g.set_pair_rows(rows)
+    g.step(7)
+    _assert_same(_state(g), _state(ref), "%s rows=%d" % (name, rows))
+
+
+def test_pairs_ragged_full_size(tlb):
+    """A 1000 x 2048 cylinder-impact lattice (16 strip columns, the last 40
+    columns wide) at its default two-step strips: 20 steps bitwise those of
+    20 single steps."""
+    p = W.cylinder_impact(nx=1000, ny=2048)
+    _say("case %s default pairs, 20 steps" % p["name"])
+    ref = tlb.from_problem(p, "fp32")
+    ref.set_pair_rows(0)
+    ref.step(20)
+    g = tlb.from_problem(p, "fp32")
+    g.step(20)
+    _assert_same(_state(g), _state(ref), "cylinder 1000x2048")
+
+
 @pytest.mark.parametrize("geometry,ny", [("channel", 12), ("periodic", 16), ("channel", 3),
                                          ("periodic", 3), ("periodic", 5), ("channel", 6)])
 def test_pairs_short_lattices(tlb, geometry, ny):
@@ -251,8 +297,9 @@ def test_batch_pairs_graph(tlb):
 
 
 def test_batch_pairs_not_applicable(tlb):
-    """FP64 members (and an FP32 batch with a 100-column member) keep one
-    step per launch when pairs are asked for, with the same results."""
+    """FP64 members keep one step per launch when pairs are asked for, with
+    the same results; an FP32 batch with a 100-column member takes pairs and
+    equals its members alone."""
     probs = [W.random_fields(64, 40, seed=4, geometry="box"), W.reduction_case(nx=64, ny=64)]
     refs = _solo_refs(tlb, probs, "fp64", 5)
     members = [tlb.from_problem(p, "fp64") for p in probs]
@@ -341,9 +388,7 @@ def test_pair_rows_arguments(tlb):
         with pytest.raises(tlb.TlbError):
             g32.set_pair_rows(bad)
     q = W.random_fields(100, 40, seed=4, geometry="box")
-    g = tlb.from_problem(q, "fp32")
-    with pytest.raises(tlb.TlbError):
-        g.set_pair_rows(16)
+    tlb.from_problem(q, "fp32").set_pair_rows(16)      # any width
     h = tlb.from_problem(W.random_fields(64, 40, seed=4, geometry="box"), "fp16dev")
     with pytest.raises(tlb.TlbError):
         h.set_pair_rows(16)
