@@ -58,18 +58,8 @@ def kernel_sha() -> str:
 
 def steps_per_launch(problem, precision: str) -> int:
     """Steps one launch of the dominant kernel advances: 2 where the library
-    uses its two-step kernel by default (FP32, a lattice that gives every
-    compute unit a 64-row strip), else 1."""
-    if precision != "fp32":
-        return 1
-    cus = 256
-    try:
-        import torch
-        cus = torch.cuda.get_device_properties(0).multi_processor_count
-    except Exception:
-        pass
-    tx = -(-problem["nx"] // 64)
-    return 2 if any(tx * -(-problem["ny"] // r) >= cus for r in (256, 128, 64)) else 1
+    uses its two-step kernel by default (FP32 storage, any lattice), else 1."""
+    return 2 if precision == "fp32" else 1
 
 
 def measured_traffic(precision: str):

@@ -240,9 +240,10 @@ tlb_status tlb_set_tile_rows(tlb_ctx* ctx, int rows);
  * columns through both steps (Eqs. 3-20, 42-45 applied twice), keeping the
  * intermediate populations in on-chip memory, so the populations cross HBM
  * once per two steps.  rows: a multiple of 4 in [8, 4096]; 0 turns it off
- * (one step per launch); -1, the default, picks the tallest of 256, 128, 64
- * rows that still gives each compute unit a strip (off for smaller
- * lattices).  Applies to FP32 populations, on lattices of any size (with
+ * (one step per launch); -1, the default, picks among 256, 128, 64, 32, 16
+ * and 8 rows the height whose launch runs the fewest strip iterations per
+ * compute unit (one workgroup per compute unit; rounds of strips times four-row
+ * groups plus four of pipeline).  Applies to FP32 populations, on lattices of any size (with
  * every optional part: velocity boundaries, lambda > 0, gravity); a context
  * of another precision steps one step per launch, and returns TLB_EINVAL for
  * rows > 0. */
