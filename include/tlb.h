@@ -287,8 +287,9 @@ tlb_status tlb_batch_step(tlb_batch* batch, int64_t nsteps);
  * tlb_batch_step advances the members two steps per launch
  * of the two-step kernel (tlb_set_pair_rows) over strips of `rows` rows of
  * every member (rows: a multiple of 4 in [8, 4096]; -1, the default: each
- * member's height rounded up to a multiple of 4, at least 8 and at most 128
- * rows), and tlb_batch_use_graph then needs a
+ * member's height rounded up to a multiple of 4, at least 8 and at most a
+ * batch height h, the h among 128, 64, 32, 16 and 8 whose launch runs the
+ * fewest strip iterations per compute unit), and tlb_batch_use_graph then needs a
  * multiple of 4 steps; with rows = 0, or a member of another precision, one step per
  * launch.  Re-registers the members (as tlb_batch_set) and drops a
  * captured graph.  TLB_EINVAL bad rows, TLB_ESTATE if a member was stepped

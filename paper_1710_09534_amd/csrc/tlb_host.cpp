@@ -273,13 +273,40 @@ int pair_rows_of(const tlb_ctx* c) {
     return c->pair_rows < 0 ? c->pair_auto_rows : c->pair_rows;
 }
 
-// Default two-step strip rows of a batch member: the lattice's height up to
-// 128 rows (measured on batches of 64^2 .. 256^2 FP32 lattices: 64-row strips
-// for 64^2, 128 for 128^2 and 256^2 were the fastest of 32, 64 and 128).
-int batch_pair_rows(int ny) { return std::min(128, std::max(8, (ny + 3) / 4 * 4)); }
+// Two-step strip rows of a batch member under a batch strip height h: the
+// member's height rounded up to 4, at least 8 and at most h.
+int member_pair_rows(int ny, int h) { return std::min(h, std::max(8, (ny + 3) / 4 * 4)); }
 
 int pair_tiles(const tlb_ctx* c, int rows) {
     return rows > 0 ? c->grid.tiles_x * ((c->ny + rows - 1) / rows) : 0;
+}
+
+// Default batch strip height: as for a lone lattice (default_pair_rows), the
+// h among 128 .. 8 rows whose launch runs the fewest strip iterations per CU,
+// here rounds of all members' strips times the longest strip's row groups
+// plus 4 of pipeline, the taller on a tie.  Batches of 256 x 64^2,
+// 128 x 128^2 and 64 x 256^2 FP32 lattices were measured fastest at 64, 128
+// and 128 rows (of 32, 64 and 128), which this picks; a batch too small to
+// fill the device gets shorter strips.
+int batch_pair_height(tlb_ctx* const* ctxs, int n, int cus) {
+    static const int cand[] = {128, 64, 32, 16, 8};
+    int best = cand[0];
+    long best_cost = -1;
+    for (int h : cand) {
+        long strips = 0;
+        int longest = 0;
+        for (int i = 0; i < n; ++i) {
+            const int r = member_pair_rows(ctxs[i]->ny, h);
+            strips += pair_tiles(ctxs[i], r);
+            longest = std::max(longest, (std::min(r, ctxs[i]->ny) + 3) / 4 + 4);
+        }
+        const long cost = (strips + cus - 1) / cus * longest;
+        if (best_cost < 0 || cost < best_cost) {
+            best = h;
+            best_cost = cost;
+        }
+    }
+    return best;
 }
 
 tlb_status upload_desc(tlb_ctx* c) {
@@ -818,7 +845,7 @@ struct tlb_batch {
     unsigned features = 0;             // union of the members' step-kernel features
     int parity = 0;                    // parity of the next step relative to the table
     int pair_rows = -1;                // two-step strip rows requested (0: one step per launch,
-                                       // -1: each member's batch_pair_rows)
+                                       // -1: member_pair_rows under batch_pair_height)
     bool pairs = false;                // pair_rows > 0 and every member can take two steps
     int pair_total_tiles = 0;          // sum of the members' two-step strips
     int hparity = 0;                   // history set of the next launch relative to the table
@@ -890,9 +917,10 @@ tlb_status tlb_batch_set(tlb_batch* b, tlb_ctx* const* ctxs, int n) {
     b->host.assign(size_t(n > 0 ? n : 1) * kDescBytes, 0);
     bool pairs = b->pair_rows != 0 && n > 0;
     for (int i = 0; i < n; ++i) pairs = pairs && pair_ok(ctxs[i]);
+    const int h = pairs && b->pair_rows < 0 ? batch_pair_height(ctxs, n, device_cus()) : 0;
     int begin = 0, pbegin = 0;
     for (int i = 0; i < n; ++i) {
-        const int pr = !pairs ? 0 : (b->pair_rows > 0 ? b->pair_rows : batch_pair_rows(ctxs[i]->ny));
+        const int pr = !pairs ? 0 : (b->pair_rows > 0 ? b->pair_rows : member_pair_rows(ctxs[i]->ny, h));
         fill_desc(ctxs[i], b->host.data() + size_t(i) * kDescBytes, begin, ctxs[i]->cur,
                   ctxs[i]->hcur, pr, pbegin);
         begin += ntiles(ctxs[i]);
