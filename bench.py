@@ -203,8 +203,8 @@ def batching_leg(tlb, torch, precision="fp32", n_lattices=256, size=64, steps=20
     b.step(steps)
     b.sync()
     t_batch = time.perf_counter() - t0
-    # the same batch with strip heights from the batch autotuner
-    rows = b.autotune_rows(10)
+    # the same batch with two-step strip heights from the batch autotuner
+    rows = b.autotune_pair_rows(10)
     b.use_graph(48)
     b.step(50)
     b.sync()
@@ -236,7 +236,7 @@ def batching_leg(tlb, torch, precision="fp32", n_lattices=256, size=64, steps=20
     nodes = n_lattices * size * size
     return {"lattices": n_lattices, "size": "%dx%d" % (size, size), "precision": precision,
             "steps": steps, "one_at_a_time_mlups": round(nodes * steps / t_solo / 1e6, 1),
-            "autotuned_rows": rows,
+            "pair_autotuned_rows": rows,
             "batched_autotuned_mlups": round(nodes * steps / t_tuned / 1e6, 1),
             "batched_mlups": round(nodes * steps / t_batch / 1e6, 1),
             "batched_one_step_per_launch_mlups": round(nodes * steps / t_one / 1e6, 1),

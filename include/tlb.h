@@ -307,6 +307,20 @@ tlb_status tlb_batch_sync(tlb_batch* batch);
  * best_rows (nullable) receives the tallest class's height.  TLB_ESTATE
  * before tlb_batch_set. */
 tlb_status tlb_batch_autotune_rows(tlb_batch* batch, int steps_per_candidate, int* best_rows);
+/* Two-step strip heights of the members, tuned for the batched launch (the
+ * launch batches take by default, see tlb_batch_set_pair_rows): members of
+ * equal height form a size class, and one pass over the classes, tallest
+ * first, gives each class the height among 8, 16, 32, 64 and 128 rows (up to
+ * the first that covers the lattice in one strip row) that makes the batched
+ * step shortest, each candidate timed over steps_per_candidate batched steps
+ * (rounded up to even; HIP events on the batch stream).  Advances every
+ * member by those steps (results do not depend on strip heights, bitwise),
+ * re-registers the members and drops a captured graph.  The tuned heights
+ * apply to members of those heights in later tlb_batch_set calls too, until
+ * tlb_batch_set_pair_rows is called.  best_rows (nullable) receives the
+ * tallest class's height.  TLB_ESTATE before tlb_batch_set, or when the batch
+ * does not take two steps per launch at its default heights. */
+tlb_status tlb_batch_autotune_pair_rows(tlb_batch* batch, int steps_per_candidate, int* best_rows);
 const char* tlb_batch_last_error(const tlb_batch* batch);
 void       tlb_batch_destroy(tlb_batch* batch);
 

@@ -849,6 +849,8 @@ struct tlb_batch {
     bool pairs = false;                // pair_rows > 0 and every member can take two steps
     int pair_total_tiles = 0;          // sum of the members' two-step strips
     int hparity = 0;                   // history set of the next launch relative to the table
+    std::vector<std::pair<int, int>> tuned_pair_rows;  // (member height, two-step strip rows)
+                                       // from tlb_batch_autotune_pair_rows, used while pair_rows == -1
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int graph_steps = 0;
@@ -920,7 +922,10 @@ tlb_status tlb_batch_set(tlb_batch* b, tlb_ctx* const* ctxs, int n) {
     const int h = pairs && b->pair_rows < 0 ? batch_pair_height(ctxs, n, device_cus()) : 0;
     int begin = 0, pbegin = 0;
     for (int i = 0; i < n; ++i) {
-        const int pr = !pairs ? 0 : (b->pair_rows > 0 ? b->pair_rows : member_pair_rows(ctxs[i]->ny, h));
+        int pr = !pairs ? 0 : (b->pair_rows > 0 ? b->pair_rows : member_pair_rows(ctxs[i]->ny, h));
+        if (pairs && b->pair_rows < 0)
+            for (const auto& t : b->tuned_pair_rows)
+                if (t.first == ctxs[i]->ny) pr = t.second;
         fill_desc(ctxs[i], b->host.data() + size_t(i) * kDescBytes, begin, ctxs[i]->cur,
                   ctxs[i]->hcur, pr, pbegin);
         begin += ntiles(ctxs[i]);
@@ -956,6 +961,7 @@ tlb_status tlb_batch_set_pair_rows(tlb_batch* b, int rows) {
         return bfail(b, TLB_EINVAL,
                      "pair strip rows must be 0, -1 or a multiple of 4 in [8, 4096]");
     b->pair_rows = rows;
+    b->tuned_pair_rows.clear();
     if (b->ctxs.empty()) return TLB_OK;
     // re-register the members: the table carries the strip layout
     const std::vector<tlb_ctx*> members = b->ctxs;
@@ -1064,6 +1070,29 @@ tlb_status tlb_batch_sync(tlb_batch* b) {
     return TLB_OK;
 }
 
+namespace {
+// mean time per step of `steps` batched steps, HIP events on the batch stream
+tlb_status time_batch_steps(tlb_batch* b, int steps, double* ms) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+    tlb_status st = e == hipSuccess ? tlb_batch_step(b, steps) : TLB_EDEVICE;
+    if (st == TLB_OK) {
+        e = hipEventRecord(e1, b->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float f = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&f, e0, e1);
+        *ms = double(f) / steps;
+        if (e != hipSuccess) st = TLB_EDEVICE;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st == TLB_EDEVICE) return bfail(b, st, "autotune timing");
+    return st;
+}
+}  // namespace
+
 tlb_status tlb_batch_autotune_rows(tlb_batch* b, int steps_per_candidate, int* best_rows) {
     if (!b || steps_per_candidate <= 0) return bfail(b, TLB_EINVAL, "bad arguments");
     if (b->ctxs.empty()) return bfail(b, TLB_ESTATE, "tlb_batch_set must precede autotune");
@@ -1098,25 +1127,7 @@ tlb_status tlb_batch_autotune_rows(tlb_batch* b, int steps_per_candidate, int* b
         }
         return tlb_batch_set(b, members.data(), int(members.size()));
     };
-    auto time_batch = [&](double* ms) -> tlb_status {
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        hipError_t e = hipEventCreate(&e0);
-        if (e == hipSuccess) e = hipEventCreate(&e1);
-        if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
-        tlb_status st = e == hipSuccess ? tlb_batch_step(b, steps_per_candidate) : TLB_EDEVICE;
-        if (st == TLB_OK) {
-            e = hipEventRecord(e1, b->stream);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float f = 0.0f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&f, e0, e1);
-            *ms = double(f) / steps_per_candidate;
-            if (e != hipSuccess) st = TLB_EDEVICE;
-        }
-        if (e0) (void)hipEventDestroy(e0);
-        if (e1) (void)hipEventDestroy(e1);
-        if (st == TLB_EDEVICE) return bfail(b, st, "autotune timing");
-        return st;
-    };
+    auto time_batch = [&](double* ms) { return time_batch_steps(b, steps_per_candidate, ms); };
     // one pass of coordinate descent over the size classes, tallest first:
     // every member of a class takes the candidate that gives the shortest
     // batched step with the other classes at their current strip heights
@@ -1143,6 +1154,58 @@ tlb_status tlb_batch_autotune_rows(tlb_batch* b, int steps_per_candidate, int* b
     if (st != TLB_OK) return st;
     if (best_rows) *best_rows = rows.empty() ? 0 : rows[0];
     return TLB_OK;
+}
+
+tlb_status tlb_batch_autotune_pair_rows(tlb_batch* b, int steps_per_candidate, int* best_rows) {
+    if (!b || steps_per_candidate <= 0) return bfail(b, TLB_EINVAL, "bad arguments");
+    if (b->ctxs.empty()) return bfail(b, TLB_ESTATE, "tlb_batch_set must precede autotune");
+    if (!b->pairs || b->pair_rows >= 0)
+        return bfail(b, TLB_ESTATE, "the batch does not take two steps per launch at default heights");
+    static const int cand[] = {8, 16, 32, 64, 128};
+    const std::vector<tlb_ctx*> members = b->ctxs;
+    const int steps = (steps_per_candidate + 1) / 2 * 2;   // whole two-step launches
+    // size classes, tallest first, starting from the heights the batch runs now
+    std::vector<std::pair<int, int>> cls;
+    for (tlb_ctx* c : members) {
+        bool seen = false;
+        for (const auto& t : cls) seen = seen || t.first == c->ny;
+        if (!seen) cls.push_back({c->ny, 0});
+    }
+    std::sort(cls.begin(), cls.end(), [](const std::pair<int, int>& a, const std::pair<int, int>& z) {
+        return a.first > z.first;
+    });
+    const int h0 = batch_pair_height(members.data(), int(members.size()), device_cus());
+    for (auto& t : cls) {
+        t.second = member_pair_rows(t.first, h0);
+        for (const auto& u : b->tuned_pair_rows)
+            if (u.first == t.first) t.second = u.second;
+    }
+    // one pass of coordinate descent over the classes: every member of a class
+    // takes the candidate that gives the shortest batched step with the other
+    // classes at their current heights (candidates stop at the first one that
+    // covers the whole lattice in one strip row)
+    for (size_t h = 0; h < cls.size(); ++h) {
+        int best = cls[h].second;
+        double best_ms = 1e30;
+        for (int r : cand) {
+            cls[h].second = r;
+            b->tuned_pair_rows = cls;
+            tlb_status st = tlb_batch_set(b, members.data(), int(members.size()));
+            double ms = 0.0;
+            if (st == TLB_OK) st = time_batch_steps(b, steps, &ms);
+            if (st != TLB_OK) return st;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = r;
+            }
+            if (r >= cls[h].first) break;
+        }
+        cls[h].second = best;
+    }
+    b->tuned_pair_rows = cls;
+    tlb_status st = tlb_batch_set(b, members.data(), int(members.size()));
+    if (st == TLB_OK && best_rows) *best_rows = cls[0].second;
+    return st;
 }
 
 const char* tlb_batch_last_error(const tlb_batch* b) {

@@ -97,6 +97,7 @@ _SIGS = {
     "tlb_batch_use_graph": (C.c_int, [_vp, C.c_int]),
     "tlb_batch_step": (C.c_int, [_vp, C.c_int64]),
     "tlb_batch_autotune_rows": (C.c_int, [_vp, C.c_int, C.POINTER(C.c_int)]),
+    "tlb_batch_autotune_pair_rows": (C.c_int, [_vp, C.c_int, C.POINTER(C.c_int)]),
     "tlb_batch_sync": (C.c_int, [_vp]),
     "tlb_batch_set_pair_rows": (C.c_int, [_vp, C.c_int]),
     "tlb_batch_last_error": (C.c_char_p, [_vp]),
@@ -360,6 +361,12 @@ class Batch:
     def autotune_rows(self, steps_per_candidate: int = 20) -> int:
         best = C.c_int()
         self._check(lib.tlb_batch_autotune_rows(self.h, int(steps_per_candidate), C.byref(best)))
+        return best.value
+
+    def autotune_pair_rows(self, steps_per_candidate: int = 20) -> int:
+        best = C.c_int()
+        self._check(lib.tlb_batch_autotune_pair_rows(self.h, int(steps_per_candidate),
+                                                     C.byref(best)))
         return best.value
 
     def sync(self):

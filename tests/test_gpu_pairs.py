@@ -276,6 +276,36 @@ def test_batch_pairs_default_rows_short_members(tlb):
         _assert_same(_state(m), r, "default-row batch pairs %s" % p["name"])
 
 
+def test_batch_autotune_pair_rows_keeps_trajectory(tlb):
+    """The two-step batch tuner times candidate strip heights per size class
+    on the batched launch: the members advance by the timed steps, stay
+    bitwise those of lone single steps, keep the tuned heights through a
+    re-registration and lose them at set_pair_rows; an FP64 batch (one step
+    per launch) is refused."""
+    probs = [W.random_obstacles(128, 96, seed=41, n_obstacles=20), W.reduction_case(nx=64, ny=64),
+             W.random_fields(100, 40, seed=42, geometry="box")]
+    members = [tlb.from_problem(p, "fp32") for p in probs]
+    batch = tlb.Batch(3)
+    batch.set(members)
+    best = batch.autotune_pair_rows(3)        # 4 steps per candidate
+    assert best in (8, 16, 32, 64, 128)
+    n = members[0].step_count
+    assert n > 0 and n % 4 == 0 and all(m.step_count == n for m in members)
+    batch.set(members)
+    batch.step(5)
+    batch.set_pair_rows(-1)
+    batch.step(3)
+    batch.sync()
+    refs = _solo_refs(tlb, probs, "fp32", n + 8)
+    for p, m, r in zip(probs, members, refs):
+        _assert_same(_state(m), r, "tuned batch pairs %s" % p["name"])
+    f64 = [tlb.from_problem(p, "fp64") for p in probs[1:]]
+    b64 = tlb.Batch(2)
+    b64.set(f64)
+    with pytest.raises(tlb.TlbError):
+        b64.autotune_pair_rows(2)
+
+
 def test_batch_pairs_graph(tlb):
     """Graph replay of two-step launches (a multiple of 4 steps) between
     plain launches: 22 batched steps equal 22 single steps; a graph of 6
