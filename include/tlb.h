@@ -271,7 +271,11 @@ typedef struct tlb_batch tlb_batch;
 size_t     tlb_batch_table_bytes(int max_lattices);
 tlb_status tlb_batch_create(int max_lattices, void* dev_table, size_t bytes,
                             void* hip_stream, tlb_batch** out);
-/* sets the member contexts (synchronizes their streams); n may be 0 */
+/* sets the member contexts (synchronizes their streams); n may be 0.  A
+ * member whose one-step strip height was never set with tlb_set_tile_rows
+ * takes one chosen for the whole batch (the height with the fewest strip
+ * iterations per workgroup slot over all members), also for its later steps
+ * on its own; results do not depend on strip heights. */
 tlb_status tlb_batch_set(tlb_batch* batch, tlb_ctx* const* ctxs, int n);
 /* captures `steps` steps (even; a multiple of 4 while the batch takes two
  * steps per launch, see tlb_batch_set_pair_rows) into a HIP graph replayed
