@@ -170,20 +170,19 @@ void fill_consts(Consts<R>& k, const tlb_ctx* c) {
 // that many strips of 64 rows uses 64, or 128 when 128-row strips number at
 // most W per CU and 64-row ones more (measured: FP64 at 1024 x 2048 and FP32
 // at 2048 x 2048 run faster as one round of taller strips).
-// A smaller lattice is latency-bound (a strip marches its rows in sequence),
-// so it takes the height among 48 .. 8 rows with the fewest iterations per
+// Otherwise the height among 64 .. 8 rows with the fewest iterations per
 // workgroup slot: rounds of strips over the W-per-CU slots times (groups of
 // four rows + about 1.6 of prologue), the taller on a tie.  Measured on
-// 64^2 .. 512^2 lattices in FP64 and FP16-dev this picks the fastest of 8 .. 32
-// rows on each (8 rows: 64^2 FP64 14.2 against 22.1 us per step at 16 rows;
-// 512^2 FP64, whose 8-row strips would take two rounds, 16 rows).
+// 64^2 .. 2048 x 1024 lattices in FP64 and FP16-dev this picks the fastest of
+// 8 .. 64 rows on each (64^2 FP64: 8 rows, 14.2 against 22.1 us per step at
+// 16; 512^2 FP64, whose 8-row strips would take two rounds, 16 rows; 1024^2
+// FP16-dev: 32 rows, 42.8 against 49.5 us at 64).
 int default_rows(int nx, int ny, int prec, int cus) {
     const int tx = (nx + kTileX - 1) / kTileX;
     auto strips = [&](int rows) { return long(tx) * ((ny + rows - 1) / rows); };
     const int slots = cus * (prec == P64 ? 1 : 2);
     if (strips(64) > slots && strips(128) <= slots) return 128;
-    if (strips(64) >= cus) return 64;
-    static const int cand[] = {48, 32, 24, 16, 12, 8};
+    static const int cand[] = {64, 48, 32, 24, 16, 12, 8};
     int best = 16;
     long best_cost = -1;
     for (int rows : cand) {
